@@ -1,0 +1,206 @@
+"""Benchmark: symmetry-reduced light-cone QAOA energy + adjoint gradient on one MI355X.
+
+Workload (default): the p=2 pair of graphs with a batch of 256 angle points each,
+  (i)  circulant C_10000(1,2) with its dihedral generators (2 edge orbits), and
+  (ii) a seeded random 3-regular graph with n=10000 (trivial group, 15000 cones of 10-14 qubits).
+One step = plan both graphs (orbits + light cones + device tables) and evaluate the energy
+and its gradient at all 256 points of each.  value = (graph, point) evaluations per second.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_fwd_adj(k: int, p: int) -> float:
+    """Algorithmic FP32 flops of one forward + adjoint cone evaluation (k qubits, depth p).
+
+    Mixer: 6 flop per amplitude per qubit (c*a - i*s*b); phase: 6 (complex multiply);
+    <Z0 Z1>: 4; Im<lambda|X_j|psi>: 4 per amplitude per qubit; Im<lambda|C|psi>: 5.
+    Forward: D_1|+> (2), p-1 full layers (6k + 6), last two-qubit mixer (12), zz (4).
+    Adjoint: beta_p inner products (8), undo last mixer on two states (24), p gamma inner
+    products (5), p-1 phases undone on two states (12), p-1 full layers undone on two
+    states with their inner products (16k).
+    """
+    n = float(1 << k)
+    fwd = 2 + (p - 1) * (6 * k + 6) + 12 + 4
+    adj = 8 + 24 + 5 * p + 12 * (p - 1) + 16 * k * (p - 1)
+    return n * (fwd + adj)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_baseline(graphs, ga, be, budget_s: float):
+    """FP64 oracle (energy + forward-mode gradient) on a bounded sample of the workload.
+
+    For each graph a fixed random sample of its terms is evaluated at one angle point and
+    the time is extrapolated to all terms with t = t_sample * M / M_sample (the paper's
+    estimator for runs that did not finish, Sec. 5).  Returns evaluations per second.
+    """
+    import oracle
+    total = 0.0
+    desc = []
+    per_graph_budget = budget_s / len(graphs)
+    for g, p, gens in graphs:
+        pl = oracle.plan(g.n, g.edges, None, gens, p, reduce=gens is not None)
+        M = len(pl["rep"])
+        rng = np.random.default_rng(0)
+        order = rng.permutation(M)
+        done, t0 = 0, time.perf_counter()
+        while done < M:
+            m = int(order[done])
+            sub = dict(pl, cones=[pl["cones"][m]], rep=pl["rep"][[m]], W=pl["W"][[m]])
+            oracle.energy_grad(sub, ga[:1], be[:1])
+            done += 1
+            if time.perf_counter() - t0 > per_graph_budget:
+                break
+        t = time.perf_counter() - t0
+        total += t * M / done
+        desc.append(f"{g.name}: {done}/{M} terms at 1 point")
+    return 1.0 / total * len(graphs), "; ".join(desc)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2101_10296_amd as Q
+    import workloads as W
+
+    (g1, p), = W.workload("c2i")[0]
+    (g2, _), = W.workload("c2ii")[0]
+    _, ga, be = W.workload("c2i")
+    P = ga.shape[0]
+    gt = torch.tensor(ga, dtype=torch.float64, device="cuda")
+    bt = torch.tensor(be, dtype=torch.float64, device="cuda")
+    graphs = [(g1, p, g1.gens()), (g2, p, None)]
+
+    def step(profile=False):
+        out = []
+        for g, pp, gens in graphs:
+            pl = Q.Plan(g.n, g.edges, p=pp, generators=gens, profile=profile)
+            E, dg, db = pl.energy_grad(gt, bt)
+            out.append((pl, E, dg, db))
+        return out
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    kernel_ms = {}
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        res = step(profile=True)
+        torch.cuda.synchronize()
+        for pl, *_ in res:
+            for k, items, ms in pl.kernel_times():
+                key = (pl.info()["n_orbits"], k)
+                d = kernel_ms.setdefault(key, [0.0, 0, pl.p])
+                d[0] += ms
+                d[1] += items
+            pl.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / a.steps * 1e3
+    evals = len(graphs) * P
+    value = evals / (dt / a.steps)
+
+    # dominant kernel: the cone-size group with the largest total time
+    (norb, kdom), (ms_dom, items_dom, pdom) = max(((k, v) for k, v in kernel_ms.items() if k[1] >= 2),
+                                                  key=lambda kv: kv[1][0])
+    flop = flops_fwd_adj(kdom, pdom) * items_dom
+    achieved = flop / (ms_dom * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": f"k_fused<K={kdom},grad>", "avg_launch_ms": round(ms_dom / a.steps, 4),
+                "items_per_launch": items_dom // a.steps}
+
+    extra = {}
+    if not a.no_plain:
+        # plain path: same kernels, one (cone, point) item per launch, 2 points of graph (ii)
+        plain = Q.Plan(g2.n, g2.edges, p=p, one_cone_at_a_time=True)
+        plain.energy_grad(gt[:1], bt[:1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain.energy_grad(gt[:2], bt[:2])
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t1) / 2
+        batched = Q.Plan(g2.n, g2.edges, p=p)
+        batched.energy_grad(gt, bt)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        batched.energy_grad(gt, bt)
+        torch.cuda.synchronize()
+        t_batched = (time.perf_counter() - t2) / P
+        extra["plain_evals_per_s_rand3reg"] = round(1.0 / t_plain, 3)
+        extra["batched_evals_per_s_rand3reg"] = round(1.0 / t_batched, 3)
+        extra["speedup_vs_plain"] = round(t_plain / t_batched, 2)
+        plain.close()
+        batched.close()
+        # symmetry speedup on the circulant: unreduced all-edge plan over the reduced one
+        red = Q.Plan(g1.n, g1.edges, p=p, generators=g1.gens())
+        unr = Q.Plan(g1.n, g1.edges, p=p, reduce=False)
+        for pl in (red, unr):
+            pl.energy_grad(gt, bt)
+        torch.cuda.synchronize()
+        ts = []
+        for pl in (red, unr):
+            t3 = time.perf_counter()
+            pl.energy_grad(gt, bt)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t3)
+        extra["symmetry_speedup_circulant"] = round(ts[1] / ts[0], 1)
+        red.close()
+        unr.close()
+
+    line = {
+        "metric": "QAOA energy+grad evals/s (batched adjoint vs plain); achieved HBM GB/s",
+        "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "p=2 energy+gradient: C_10000(1,2) reduced (2 orbits) + random 3-regular "
+                               "n=10000 (15000 cones), 256 angle points each, plan included per step",
+                   "points_per_graph": P, "p": p, "parallelism": "single GPU"},
+        "roofline": roofline,
+    }
+    line.update(extra)
+    if not a.no_cpu_baseline:
+        v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
+        line["cpu_baseline"] = {"value": round(v, 6), "unit": "evals/s", "cores": 1, "kind": "oracle",
+                                "sample": sample + f" (FP64 numpy, {cpu_model()}, extrapolated to all terms)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * qaoa.h - C ABI of libqaoa.so: symmetry-reduced light-cone QAOA MaxCut energy and
+ * its gradient on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Shaydulin & Wild, "Exploiting Symmetry Reduces the Cost of Training
+ * QAOA", arXiv:2101.10296):
+ *   - QAOA state |beta,gamma>_p = U_B(beta_p) U_P(gamma_p) ... U_B(beta_1) U_P(gamma_1) |+>^n
+ *     with U_P(gamma) = exp(-i gamma H), U_B(beta) = prod_j exp(-i beta X_j)   (Sec. 2.2)
+ *   - MaxCut H = 1/2 sum_{(u,v) in E} w_uv (I - Z_u Z_v)                      (Sec. 2.4;
+ *     weights J_uv as in Sec. 4, Eq. 6)
+ *   - each term <Z_u Z_v> is evaluated on its reverse causal cone, the radius-p ball
+ *     around {u, v}                                                             (Sec. 2.3)
+ *   - terms related by a graph automorphism have equal expectation (Sec. 3, Theorem 1),
+ *     so only one representative per edge orbit is evaluated and weighted by the
+ *     orbit's total weight                                   (Sec. 3, reduced-energy display)
+ *
+ * Conventions
+ *   - All functions return a qaoa_status; on failure nothing is written to outputs and
+ *     qaoa_last_error() returns a thread-local description.
+ *   - The caller owns every buffer passed in.  qaoa_plan_lightcones copies what it needs;
+ *     host inputs may be freed as soon as it returns.
+ *   - Angle and output pointers of qaoa_energy / qaoa_energy_grad are DEVICE pointers on
+ *     the current HIP device.  Work is enqueued on `stream` (NULL = default stream) and
+ *     the outputs are valid once that stream has been synchronised.
+ *   - One energy call may be in flight per plan (the plan owns its scratch buffers).
+ *   - Angle layout: gamma[i * p + l], beta[i * p + l] for point i and layer l (0-based).
+ *   - Energy returned: E(gamma, beta) = <H_MaxCut> = sum_m W_m (1 - zz_m) / 2 with
+ *     zz_m = <Z_u Z_v> of the representative of orbit m and W_m the sum of the weights
+ *     of the orbit's edges.  The phase on |x> is exp(-i gamma C(x)) with C(x) the weighted
+ *     cut (the paper's U_P with H = H_MaxCut); a convention exp(-i g' sum w ZZ) maps to
+ *     gamma = -2 g' up to a global phase.
+ */
+#ifndef QAOA_H
+#define QAOA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qaoa_status;
+enum {
+    QAOA_OK = 0,
+    QAOA_EINVAL = -1,   /* bad sizes or ids, self-loop, duplicate edge, p < 1, n_points < 1,
+                           non-integer weights (the GPU path needs integer cut values) */
+    QAOA_ENOTAUT = -2,  /* a generator is not a weight-preserving automorphism */
+    QAOA_ECONE = -3,    /* a light cone exceeds max_cone_qubits, or its cut range exceeds 255 */
+    QAOA_ENOMEM = -4,   /* not even one work item fits the memory budget / device memory */
+    QAOA_EHIP = -5      /* HIP runtime error (no device, launch failure, ...) */
+};
+
+/* HIP stream handle; the same type as hipStream_t. */
+typedef struct ihipStream_t* qaoa_stream_t;
+
+/* Opaque plan, owned by the library until qaoa_plan_destroy. */
+typedef struct qaoa_plan_s* qaoa_plan_t;
+
+/* Problem statement (Sec. 2.4 graph, Sec. 4 weights, Sec. 2.2 depth, Sec. 3 symmetry
+ * group given by generators).  All pointers are HOST memory. */
+typedef struct {
+    int32_t n_nodes;              /* |V| >= 1 */
+    int64_t n_edges;              /* |E| >= 0; the input order is the edge index */
+    const int32_t* edge_u;        /* [n_edges], 0 <= id < n_nodes */
+    const int32_t* edge_v;        /* [n_edges] */
+    const double* edge_w;         /* [n_edges] integer-valued weights, or NULL = unit weights */
+    int32_t n_generators;         /* >= 0 */
+    const int32_t* generators;    /* row-major [n_generators][n_nodes]: image of node i under
+                                     generator g; NULL / 0 = trivial group */
+    int32_t p;                    /* QAOA depth >= 1 */
+} qaoa_problem;
+
+/* Planning options.  Pass NULL for the defaults (qaoa_plan_opts_default). */
+typedef struct {
+    int64_t mem_budget_bytes;     /* device bytes the plan may use for cone states;
+                                     0 = 85 % of free device memory at first use */
+    int32_t reduce;               /* 1 = one term per edge orbit (default); 0 = every edge is
+                                     its own term (the plain, unreduced light-cone sum) */
+    int32_t max_cone_qubits;      /* 0 = 30 */
+    int32_t k_lds_max;            /* cones with k <= this run entirely inside one workgroup
+                                     (0 = default 14, at most 14) */
+    int32_t checkpoint_mode;      /* adjoint of cones held in HBM: 0 = uncompute (default:
+                                     the forward state is recovered by inverse layers),
+                                     1 = keep one state per pass when it fits the budget */
+    int32_t one_cone_at_a_time;   /* 1 = plain GPU path: one launch per (cone, point) */
+    int32_t profile;              /* 1 = record HIP events around every kernel group of each
+                                     energy call (read with qaoa_plan_kernel_times) */
+} qaoa_plan_opts;
+
+typedef struct {
+    int32_t n_nodes;
+    int32_t p;
+    int64_t n_edges;
+    int64_t n_orbits;             /* M: number of evaluated terms */
+    int32_t min_k, max_k;         /* smallest / largest cone (qubits) */
+    int64_t k_hist[31];           /* number of cones with k qubits, k = 0..30 */
+    double total_weight;          /* sum of all edge weights */
+    int32_t cut_min, cut_max;     /* range of cut values over all cones */
+    int64_t n_hbm_cones;          /* cones too large for one workgroup (state kept in HBM) */
+    int64_t device_bytes;         /* descriptor and table bytes resident on the device */
+} qaoa_plan_info;
+
+void qaoa_plan_opts_default(qaoa_plan_opts* opts);
+
+/* Build a plan: canonicalise the edges (u < v), verify every generator (a permutation of
+ * the nodes mapping E onto E and keeping each weight bit for bit), form edge orbits
+ * (representative = smallest edge index, orbits numbered by ascending representative),
+ * and extract one light cone per orbit: qubit 0 = u, qubit 1 = v, the rest of the
+ * radius-p ball by (distance, node id); every induced edge is a cone edge.
+ * Host-only work; device tables are built on the first energy call.
+ * Errors: EINVAL, ENOTAUT, ECONE. */
+qaoa_status qaoa_plan_lightcones(const qaoa_problem* problem, const qaoa_plan_opts* opts,
+                                 qaoa_plan_t* out);
+
+/* Summary of a plan (host). */
+qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out);
+
+/* Orbit assignment (host buffers): edge_orbit[n_edges], orbit_rep[n_orbits],
+ * orbit_size[n_orbits].  Any pointer may be NULL. */
+qaoa_status qaoa_plan_orbits(qaoa_plan_t plan, int32_t* edge_orbit, int64_t* orbit_rep,
+                             int64_t* orbit_size);
+
+/* Cone of orbit m (host buffers): *k_out = qubits; nodes[i] = graph node of qubit i
+ * (capacity entries are written at most); *n_cone_edges = induced edges.
+ * EINVAL if m is out of range. */
+qaoa_status qaoa_plan_cone(qaoa_plan_t plan, int64_t orbit, int32_t* k_out, int32_t* nodes,
+                           int32_t capacity, int32_t* n_cone_edges);
+
+/* Energy at n_points angle points (Sec. 2.2 ansatz, Sec. 3 reduced sum).
+ * gamma, beta: device [n_points * p]; energy: device [n_points];
+ * term_zz: device [n_points * n_orbits] (point-major: term_zz[i * n_orbits + m]) or NULL.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+qaoa_status qaoa_energy(qaoa_plan_t plan, int64_t n_points, const double* gamma,
+                        const double* beta, double* energy, double* term_zz,
+                        qaoa_stream_t stream);
+
+/* Energy and its gradient dE/dgamma_l, dE/dbeta_l (device [n_points * p] each) by an
+ * adjoint sweep that recovers the forward state by applying inverse layers.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+qaoa_status qaoa_energy_grad(qaoa_plan_t plan, int64_t n_points, const double* gamma,
+                             const double* beta, double* energy, double* dgamma,
+                             double* dbeta, qaoa_stream_t stream);
+
+/* Diagnostics for plans built with opts.profile = 1: per kernel group of the last energy
+ * call (one group per cone size k, plus the table and combine kernels, reported with
+ * k = -1 and k = -2), the cone size, the number of (cone, point) items and the elapsed
+ * milliseconds between HIP events recorded on the call's stream around the group.
+ * Blocks until those events have completed.  *n_out = number of groups (at most cap
+ * are written).  EINVAL if the plan was not built with profiling or has not run. */
+qaoa_status qaoa_plan_kernel_times(qaoa_plan_t plan, int32_t cap, int32_t* k_out, int64_t* items_out,
+                                   double* ms_out, int32_t* n_out);
+
+/* Release the plan and everything it owns on the device (synchronises the device). */
+void qaoa_plan_destroy(qaoa_plan_t plan);
+
+/* Text of the last failure on this thread ("" if none). */
+const char* qaoa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAOA_H */

@@ -1,0 +1,209 @@
+"""Symmetry-reduced light-cone QAOA MaxCut energy and gradient on AMD Instinct MI355X.
+
+Python binding of libqaoa.so (include/qaoa.h).  Every step of the computation runs in
+the library's HIP kernels; this module only marshals arguments.  PyTorch supplies device
+memory and the current HIP stream.
+
+    plan = Plan(n, edges, p=2, generators=gens)        # orbits + light cones (host)
+    E = plan.energy(gamma, beta)                         # gamma, beta: cuda float64 [P, p]
+    E, dgamma, dbeta = plan.energy_grad(gamma, beta)
+    E = qaoa_energy(plan, gamma, beta)                   # differentiable (autograd)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _capi
+from ._capi import (QAOA_EHIP, QAOA_ECONE, QAOA_EINVAL, QAOA_ENOMEM, QAOA_ENOTAUT,  # noqa: F401
+                    QAOA_OK, STATUS_NAMES)
+
+__all__ = ["Plan", "QaoaError", "qaoa_energy", "QAOAEnergyFn", "library_path"]
+
+
+def library_path() -> str:
+    return _capi.LIB_PATH
+
+
+class QaoaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(st: int):
+    if st != QAOA_OK:
+        raise QaoaError(st, _capi.lib().qaoa_last_error().decode(errors="replace"))
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+class Plan:
+    """A planned problem: canonical edges, edge orbits and one light cone per orbit."""
+
+    def __init__(self, n_nodes: int, edges, p: int, weights=None, generators=None, *, reduce: bool = True,
+                 max_cone_qubits: int = 30, k_lds_max: int = 14, mem_budget_bytes: int = 0,
+                 checkpoint_mode: int = 0, one_cone_at_a_time: bool = False, profile: bool = False):
+        L = _capi.lib()
+        e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+        self._u = _i32(e[:, 0])
+        self._v = _i32(e[:, 1])
+        self._w = None if weights is None else np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        g = None if generators is None else _i32(generators).reshape(-1, int(n_nodes))
+        self._g = g
+        pr = _capi.Problem()
+        pr.n_nodes = int(n_nodes)
+        pr.n_edges = int(e.shape[0])
+        pr.edge_u = self._u.ctypes.data_as(C.POINTER(C.c_int32))
+        pr.edge_v = self._v.ctypes.data_as(C.POINTER(C.c_int32))
+        pr.edge_w = None if self._w is None else self._w.ctypes.data_as(C.POINTER(C.c_double))
+        pr.n_generators = 0 if g is None else int(g.shape[0])
+        pr.generators = None if g is None or g.size == 0 else g.ctypes.data_as(C.POINTER(C.c_int32))
+        pr.p = int(p)
+        o = _capi.PlanOpts()
+        L.qaoa_plan_opts_default(C.byref(o))
+        o.reduce = int(bool(reduce))
+        o.max_cone_qubits = int(max_cone_qubits)
+        o.k_lds_max = int(k_lds_max)
+        o.mem_budget_bytes = int(mem_budget_bytes)
+        o.checkpoint_mode = int(checkpoint_mode)
+        o.one_cone_at_a_time = int(bool(one_cone_at_a_time))
+        o.profile = int(bool(profile))
+        h = C.c_void_p()
+        _check(L.qaoa_plan_lightcones(C.byref(pr), C.byref(o), C.byref(h)))
+        self._h = h
+        self.p = int(p)
+        self.n_nodes = int(n_nodes)
+        self.n_edges = int(e.shape[0])
+        self.n_orbits = int(self.info()["n_orbits"])
+
+    # ---------------------------------------------------------------- host queries
+    def info(self) -> dict:
+        inf = _capi.PlanInfo()
+        _check(_capi.lib().qaoa_plan_query(self._h, C.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in _capi.PlanInfo._fields_ if f != "k_hist"}
+        d["k_hist"] = list(inf.k_hist)
+        return d
+
+    def orbits(self):
+        """(edge_orbit int32 [m], rep int64 [M], size int64 [M])."""
+        M = self.info()["n_orbits"]
+        eo = np.zeros(self.n_edges, np.int32)
+        rep = np.zeros(M, np.int64)
+        size = np.zeros(M, np.int64)
+        _check(_capi.lib().qaoa_plan_orbits(self._h, eo.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            rep.ctypes.data_as(C.POINTER(C.c_int64)),
+                                            size.ctypes.data_as(C.POINTER(C.c_int64))))
+        return eo, rep, size
+
+    def cone(self, m: int):
+        """(k, nodes int32 [k], n_cone_edges) of the cone of orbit m."""
+        k = C.c_int32()
+        ne = C.c_int32()
+        nodes = np.zeros(31, np.int32)
+        _check(_capi.lib().qaoa_plan_cone(self._h, int(m), C.byref(k), nodes.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          31, C.byref(ne)))
+        return int(k.value), nodes[: k.value].copy(), int(ne.value)
+
+    def kernel_times(self):
+        """[(k, items, ms)] per kernel group of the last call (plans built with profile=True);
+        k = -1 is the angle-table kernel, k = -2 the orbit-weighted combination."""
+        cap = 64
+        ks = np.zeros(cap, np.int32)
+        it = np.zeros(cap, np.int64)
+        ms = np.zeros(cap, np.float64)
+        n = C.c_int32()
+        _check(_capi.lib().qaoa_plan_kernel_times(self._h, cap, ks.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  it.ctypes.data_as(C.POINTER(C.c_int64)),
+                                                  ms.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+        return [(int(ks[i]), int(it[i]), float(ms[i])) for i in range(min(n.value, cap))]
+
+    # ---------------------------------------------------------------- device evaluation
+    def _angles(self, gamma, beta):
+        import torch
+        if not (isinstance(gamma, torch.Tensor) and isinstance(beta, torch.Tensor)):
+            raise TypeError("gamma and beta must be torch tensors on a HIP device")
+        if gamma.device.type != "cuda" or beta.device.type != "cuda":
+            raise ValueError("gamma and beta must live on the GPU")
+        g = gamma.detach().to(torch.float64).reshape(-1, self.p).contiguous()
+        b = beta.detach().to(torch.float64).reshape(-1, self.p).contiguous()
+        if g.shape != b.shape:
+            raise ValueError("gamma and beta must have the same shape [P, p]")
+        return g, b
+
+    def energy(self, gamma, beta, term_zz: bool = False):
+        """E [P] (and per-orbit <ZZ> [P, M] if term_zz) as cuda float64 tensors."""
+        import torch
+        g, b = self._angles(gamma, beta)
+        P = g.shape[0]
+        E = torch.empty(P, dtype=torch.float64, device=g.device)
+        zz = torch.empty((P, max(self.n_orbits, 1)), dtype=torch.float64, device=g.device) if term_zz else None
+        stream = torch.cuda.current_stream(g.device).cuda_stream
+        _check(_capi.lib().qaoa_energy(self._h, P, g.data_ptr(), b.data_ptr(), E.data_ptr(),
+                                       None if zz is None else zz.data_ptr(), stream))
+        return (E, zz[:, : self.n_orbits]) if term_zz else E
+
+    def energy_grad(self, gamma, beta):
+        """(E [P], dE/dgamma [P, p], dE/dbeta [P, p]) as cuda float64 tensors."""
+        import torch
+        g, b = self._angles(gamma, beta)
+        P = g.shape[0]
+        E = torch.empty(P, dtype=torch.float64, device=g.device)
+        dg = torch.empty_like(g)
+        db = torch.empty_like(b)
+        stream = torch.cuda.current_stream(g.device).cuda_stream
+        _check(_capi.lib().qaoa_energy_grad(self._h, P, g.data_ptr(), b.data_ptr(), E.data_ptr(),
+                                            dg.data_ptr(), db.data_ptr(), stream))
+        return E, dg, db
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _capi.lib().qaoa_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd_fn():
+    import torch
+
+    class QAOAEnergyFn(torch.autograd.Function):
+        """E(gamma, beta) with the adjoint gradient computed in the same library call."""
+
+        @staticmethod
+        def forward(ctx, gamma, beta, plan):
+            E, dg, db = plan.energy_grad(gamma, beta)
+            ctx.save_for_backward(dg, db)
+            ctx.shapes = (gamma.shape, beta.shape, gamma.dtype, beta.dtype)
+            return E
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            dg, db = ctx.saved_tensors
+            gs, bs, gdt, bdt = ctx.shapes
+            go = grad_out.to(torch.float64).reshape(-1, 1)
+            return (go * dg).reshape(gs).to(gdt), (go * db).reshape(bs).to(bdt), None
+
+    return QAOAEnergyFn
+
+
+_FN = None
+
+
+def QAOAEnergyFn():  # noqa: N802 - returns the autograd Function class
+    global _FN
+    if _FN is None:
+        _FN = _autograd_fn()
+    return _FN
+
+
+def qaoa_energy(plan: Plan, gamma, beta):
+    """Differentiable energy: gamma, beta [P, p] (cuda) -> E [P]."""
+    return QAOAEnergyFn().apply(gamma, beta, plan)

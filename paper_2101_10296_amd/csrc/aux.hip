@@ -1,0 +1,113 @@
+// Small kernels around the light-cone kernels: per-call angle tables, per-plan cut
+// tables, and the orbit-weighted combination of term values into E and dE.
+#include "device.hpp"
+
+namespace qaoa {
+
+// phase[(i*p + l)*R + j] = exp(-i gamma_{i,l} c), c = cmin + j  (U_P on a basis state with
+// cut value c, Sec. 2.2 / 2.4), computed in FP64 and rounded to FP32;
+// mix[i*p + l] = (tau, |kappa|^2) of exp(-i beta_{i,l} X) = kappa X^e (1 - i tau X) (Sec. 2.2):
+// tau = tan beta, |kappa|^2 = cos^2 beta when |cos beta| >= |sin beta|, otherwise
+// tau = -cot beta, |kappa|^2 = sin^2 beta.
+__global__ void k_tables(const double* __restrict__ gamma, const double* __restrict__ beta,
+                         int64_t n_pl, int32_t R, int32_t cmin, float2* __restrict__ phase,
+                         float2* __restrict__ mix) {
+    const int64_t total = n_pl * R;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t pl = t / R;
+        const int32_t j = static_cast<int32_t>(t - pl * R);
+        double s, c;
+        sincos(gamma[pl] * static_cast<double>(cmin + j), &s, &c);
+        phase[t] = make_float2(static_cast<float>(c), static_cast<float>(-s));
+        if (j == 0) {
+            // exp(-i beta X) = kappa X^e (1 - i tau X): the bounded factorisation
+            double sb, cb;
+            sincos(beta[pl], &sb, &cb);
+            double t, k2;
+            if (fabs(cb) >= fabs(sb)) {
+                t = sb / cb;
+                k2 = cb * cb;
+            } else {
+                t = -cb / sb;
+                k2 = sb * sb;
+            }
+            mix[pl] = make_float2(static_cast<float>(t), static_cast<float>(k2));
+        }
+    }
+}
+
+// Cut table of cone c: table[x] = C(x) - cut_min for every basis state x of its k qubits,
+// C(x) = sum over cone edges (a, b) of w_ab [x_a != x_b]  (MaxCut cost, Sec. 2.4).
+__global__ void k_cut_tables(const ConeDev* __restrict__ cones, const int32_t* __restrict__ ea,
+                             const int32_t* __restrict__ eb, const int32_t* __restrict__ ew,
+                             uint8_t* __restrict__ tables) {
+    const ConeDev cd = cones[blockIdx.x];
+    const uint32_t N = 1u << cd.k;
+    uint8_t* out = tables + cd.cut_off;
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) {
+        int32_t c = 0;
+        for (int32_t e = 0; e < cd.n_edges; ++e) {
+            const int32_t a = ea[cd.edge_off + e], b = eb[cd.edge_off + e];
+            c += ew[cd.edge_off + e] * static_cast<int32_t>(((x >> a) ^ (x >> b)) & 1u);
+        }
+        out[x] = static_cast<uint8_t>(c - cd.cut_min);
+    }
+}
+
+// Block y == 0: energy[i] = sum_m W_m (1 - zz[i][m]) / 2            (Sec. 3 reduced sum)
+// Block y == 1 + j: -1/2 sum_m W_m g[i][j][m] -> dgamma (j < p) or dbeta (j >= p)
+// Fixed-order reduction (deterministic): thread t sums m = t, t + 256, ...; then a tree.
+__global__ void __launch_bounds__(256)
+k_combine(const double* __restrict__ W, const double* __restrict__ zz, const double* __restrict__ g,
+          int32_t M, int32_t p, double* __restrict__ energy, double* __restrict__ dgamma,
+          double* __restrict__ dbeta) {
+    __shared__ double sh[256];
+    const int i = blockIdx.x;
+    const int y = blockIdx.y;
+    const double* src = (y == 0) ? zz + static_cast<size_t>(i) * M
+                                 : g + (static_cast<size_t>(i) * 2 * p + (y - 1)) * M;
+    double acc = 0.0;
+    for (int m = threadIdx.x; m < M; m += 256) {
+        acc += (y == 0) ? W[m] * (1.0 - src[m]) * 0.5 : -0.5 * W[m] * src[m];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (y == 0) energy[i] = sh[0];
+        else if (y - 1 < p) dgamma[static_cast<size_t>(i) * p + (y - 1)] = sh[0];
+        else dbeta[static_cast<size_t>(i) * p + (y - 1 - p)] = sh[0];
+    }
+}
+
+hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, int32_t R, int32_t cmin,
+                         float2* phase, float2* mix, hipStream_t st) {
+    const int64_t total = n_pl * R;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_tables, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, gamma, beta, n_pl, R,
+                       cmin, phase, mix);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
+                             const int32_t* ew, uint8_t* tables, hipStream_t st) {
+    if (n_cones <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cut_tables, dim3(static_cast<unsigned>(n_cones)), dim3(256), 0, st, cones, ea, eb, ew,
+                       tables);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
+                          double* energy, double* dgamma, double* dbeta, hipStream_t st) {
+    const unsigned ny = (g != nullptr) ? static_cast<unsigned>(1 + 2 * p) : 1u;
+    hipLaunchKernelGGL(k_combine, dim3(static_cast<unsigned>(P), ny), dim3(256), 0, st, W, zz, g, M, p, energy,
+                       dgamma, dbeta);
+    return hipGetLastError();
+}
+
+}  // namespace qaoa

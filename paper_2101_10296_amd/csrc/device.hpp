@@ -1,0 +1,34 @@
+// Device-side data shared by the launchers and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qaoa {
+
+// One light cone as seen by the kernels.
+struct ConeDev {
+    int32_t orbit;      // term index m (output column)
+    int32_t k;          // qubits
+    int32_t edge_off;   // first cone edge in the flattened edge arrays
+    int32_t n_edges;    // induced edges
+    int64_t cut_off;    // byte offset of the cone's cut table (workgroup-resident cones)
+    int32_t cut_shift;  // cone.cut_min - plan.cut_min: offset into a phase table row
+    int32_t cut_min;    // smallest possible cut value of the cone
+    int32_t cut_range;  // cut_max - cut_min + 1
+    int32_t pad_;
+};
+
+// Arguments of one energy evaluation that every kernel needs.
+struct EvalArgs {
+    int32_t P;              // angle points
+    int32_t p;              // depth
+    int32_t M;              // terms (orbits)
+    int32_t R;              // phase-table row length (global cut range + 1)
+    const float2* phase;    // [P][p][R]: exp(-i gamma_l c), c = plan.cut_min + index
+    const float2* mix;      // [P][p]: (cos beta_l, sin beta_l)
+    double* zz;             // [P][M]
+    double* g;              // [P][2p][M]: d zz / d gamma_l (l < p), d zz / d beta_l (p <= l < 2p)
+};
+
+}  // namespace qaoa

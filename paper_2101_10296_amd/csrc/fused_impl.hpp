@@ -1,0 +1,503 @@
+// Workgroup-resident light-cone kernel: one (cone, angle point) item is simulated
+// entirely inside a workgroup, forward and (optionally) adjoint, for cones of up to 14
+// qubits.
+//
+// State layout.  An item's 2^K complex64 amplitudes are spread over TPI threads with
+// A = 2^AB amplitudes each in registers.  In "stage" st the amplitude held by thread
+// tau in register r has basis index q = rotl_K((tau << AB) | r, st * AB): the AB
+// register bits cover qubits st*AB .. st*AB+AB-1, so the single-qubit mixers of those
+// qubits are butterflies between registers.  Moving between stages is a transpose
+// through LDS (XOR-swizzled against bank conflicts).  Layers alternate the stage order
+// so that consecutive layers share a stage and the last full layer ends in stage 0,
+// which holds qubits 0 and 1 (u and v) for the final two-qubit mixer and <Z_0 Z_1>.
+//
+// Steps (Sec. 2.2 ansatz with the MaxCut cost of Sec. 2.4, on the cone of Sec. 2.3):
+//   psi = 2^{-K/2} exp(-i gamma_1 C(x))                 (|+>^K then U_P(gamma_1))
+//   for l = 1..p-1: mixer exp(-i beta_l X_j) on every qubit, then exp(-i gamma_{l+1} C)
+//   last layer: mixer on qubits 0 and 1 only (the others commute through Z_0 Z_1)
+//   zz = sum_x |psi_x|^2 (1 - 2 (x_0 xor x_1)), accumulated in FP64
+// Adjoint (GRAD): lambda = Z_0 Z_1 psi, then the layers are undone in reverse on both
+// psi and lambda, with
+//   d zz / d beta_l  = 2 Im <lambda| sum_j X_j |psi>   (taken while undoing mixer l)
+//   d zz / d gamma_l = 2 Im <lambda| C |psi>          (after mixer l is undone)
+// The forward state is recovered by the inverse layers, not stored.
+#pragma once
+
+#include "device.hpp"
+
+#include <type_traits>
+
+namespace qaoa {
+
+// G = 1 for the adjoint kernels, which hold two states and use 16 amplitudes per thread.
+template <int K, int G = 0>
+struct Fz {
+    static constexpr int AB_MAX = G ? 4 : 5;
+    static constexpr int AB = K < AB_MAX ? K : AB_MAX;  // register bits
+    static constexpr int A = 1 << AB;              // amplitudes per thread per state
+    static constexpr int TB = K - AB;              // thread bits per item
+    static constexpr int TPI = 1 << TB;            // threads per item
+    static constexpr int WG = TPI > 64 ? TPI : 64;
+    static constexpr int IPW = WG / TPI;           // items per workgroup
+    static constexpr int S = (K + AB - 1) / AB;    // stages
+    static constexpr uint32_t N = 1u << K;
+    static constexpr uint32_t NPAD = N + (N >> 5) + (N >> 10);  // padded LDS item buffer
+};
+
+template <int K>
+__device__ constexpr uint32_t rotl(uint32_t x, int s) {
+    return s == 0 ? x : (((x << s) | (x >> (K - s))) & ((1u << K) - 1u));
+}
+template <int K, int G, int ST>
+__device__ constexpr uint32_t roff(int r) { return rotl<K>(static_cast<uint32_t>(r), ST * Fz<K, G>::AB); }
+template <int K, int G, int ST>
+__device__ __forceinline__ uint32_t tbase(uint32_t tau) { return rotl<K>(tau << Fz<K, G>::AB, ST * Fz<K, G>::AB); }
+
+// LDS padding against bank conflicts: one slot per 32 and one per 1024 entries.  It is
+// additive over indices with disjoint bits, so pad(base | off) = pad(base) + pad(off) and
+// every register of a transpose is addressed by one base register plus an immediate.
+__device__ constexpr uint32_t pad(uint32_t q) { return q + (q >> 5) + (q >> 10); }
+
+template <int NS, class F>
+__device__ __forceinline__ void sdispatch(int st, F&& f) {
+    if constexpr (NS >= 1) { if (st == 0) { f(std::integral_constant<int, 0>{}); return; } }
+    if constexpr (NS >= 2) { if (st == 1) { f(std::integral_constant<int, 1>{}); return; } }
+    if constexpr (NS >= 3) { if (st == 2) { f(std::integral_constant<int, 2>{}); return; } }
+}
+
+// Factored single-qubit mixer.  exp(-i beta X) = kappa X^e (1 - i tau X) with
+//   |cos beta| >= |sin beta|: kappa = cos beta,     e = 0, tau = tan beta
+//   otherwise:                kappa = -i sin beta,  e = 1, tau = -cot beta,
+// so |tau| <= 1 and the butterfly is psi'_x = psi_x - i tau psi_{x xor 2^j}: one FMA per
+// output component.  A full layer multiplies the state by kappa^k X^(e k); every cone
+// state is invariant under flipping all cone qubits (|+>, C(x) and the mixer are), so
+// X^(k) acts as the identity, and the real factor |kappa|^k is folded into the next
+// phase row.  Undoing a layer uses tau -> -tau and gains a factor 1/|kappa|^2 per qubit.
+__device__ __forceinline__ void bfly(float2& a, float2& b, float t) {
+    const float2 a0 = a, b0 = b;
+    a.x = fmaf(t, b0.y, a0.x);
+    a.y = fmaf(-t, b0.x, a0.y);
+    b.x = fmaf(t, a0.y, b0.x);
+    b.y = fmaf(-t, a0.x, b0.y);
+}
+
+// Im(conj(la) pb) + Im(conj(lb) pa): the pair's share of Im <lambda| X_j |psi>.
+__device__ __forceinline__ float xterm(float2 la, float2 lb, float2 pa, float2 pb) {
+    return fmaf(la.x, pb.y, -la.y * pb.x) + fmaf(lb.x, pa.y, -lb.y * pa.x);
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+
+template <int K, int G, int ST, int A>
+__device__ __forceinline__ void mix_stage(float2 (&v)[A], float t) {
+    constexpr int AB = Fz<K, G>::AB;
+#pragma unroll
+    for (int i = 0; i < AB; ++i) {
+        if (ST * AB + i >= K) continue;  // wrapped bit: handled in stage 0
+        int nb = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                bfly(v[r], v[r | (1 << i)], t);
+                if ((++nb & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Undo the mixer on the stage's qubits for psi and lambda; returns the stage's share of
+// Im <lambda| sum_j X_j |psi>.  X_j commutes with its own rotation, so the pair's term is
+// taken after the butterfly; every undone qubit scales both states by 1/|kappa|^2, which
+// the running weight w (= |kappa|^{2m} after m qubits) compensates.
+template <int K, int G, int ST, int A>
+__device__ __forceinline__ float unmix_stage2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w) {
+    constexpr int AB = Fz<K, G>::AB;
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < AB; ++i) {
+        if (ST * AB + i >= K) continue;
+        float a0 = 0.f, a1 = 0.f;
+        int np = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                const int r2 = r | (1 << i);
+                bfly(f[r], f[r2], -t);
+                bfly(l[r], l[r2], -t);
+                if (np++ & 1) a1 += xterm(l[r], l[r2], f[r], f[r2]);
+                else a0 += xterm(l[r], l[r2], f[r], f[r2]);
+                if ((np & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        w *= k2;
+        acc = fmaf(w, a0 + a1, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// The transpose bases are loop-invariant; an empty asm makes them opaque so that the
+// compiler keeps one base register plus immediate offsets instead of hoisting one
+// address register per amplitude out of the layer loops.
+__device__ __forceinline__ uint32_t opaque_u32(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+template <int K, int G, int FROM, int TO, int A>
+__device__ __forceinline__ void xpose(float2 (&v)[A], float2* xb, uint32_t tau) {
+    float2* pf = xb + opaque_u32(pad(tbase<K, G, FROM>(tau)));
+    const float2* pt = xb + opaque_u32(pad(tbase<K, G, TO>(tau)));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) v[r] = pt[pad(roff<K, G, TO>(r))];
+}
+
+
+// Cut values of the thread's amplitudes in stage ST, packed four bytes per register.
+template <int K, int G, int ST, int A>
+__device__ __forceinline__ void load_cuts(uint32_t (&pk)[(A + 3) / 4], const uint8_t* cut, uint32_t tau) {
+    const uint8_t* cb = cut + tbase<K, G, ST>(tau);
+#pragma unroll
+    for (int w = 0; w < (A + 3) / 4; ++w) pk[w] = 0u;
+#pragma unroll
+    for (int r = 0; r < A; ++r) pk[r >> 2] |= static_cast<uint32_t>(cb[roff<K, G, ST>(r)]) << (8 * (r & 3));
+}
+
+// The packed cut words are loop-invariant; hiding them behind an empty asm at every use
+// keeps the compiler from hoisting 2 x A derived addresses into live registers.
+template <int A>
+__device__ __forceinline__ void opaque(uint32_t (&pk)[(A + 3) / 4]) {
+#pragma unroll
+    for (int w = 0; w < (A + 3) / 4; ++w) asm volatile("" : "+v"(pk[w]));
+}
+
+template <int A>
+__device__ __forceinline__ uint32_t cutv(const uint32_t (&pk)[(A + 3) / 4], int r) {
+    return (pk[r >> 2] >> (8 * (r & 3))) & 255u;
+}
+
+// psi = sc * row[C(x)]: D_1 applied to the uniform state.
+template <int A>
+__device__ __forceinline__ void gen_stage(float2 (&f)[A], uint32_t (&pk)[(A + 3) / 4], const float2* row,
+                                          float sc) {
+    opaque<A>(pk);
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 t = row[cutv<A>(pk, r)];
+        f[r] = make_float2(sc * t.x, sc * t.y);
+        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int A>
+__device__ __forceinline__ void phase_stage(float2 (&f)[A], uint32_t (&pk)[(A + 3) / 4], const float2* row,
+                                            float sc) {
+    opaque<A>(pk);
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 t = row[cutv<A>(pk, r)];
+        f[r] = cmul(f[r], make_float2(sc * t.x, sc * t.y));
+        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Returns the thread's share of Im <lambda| C |psi>; then, with UNDO, applies D^dagger
+// scaled by sc (row holds exp(-i gamma c)) to both states.
+template <bool UNDO, int A>
+__device__ __forceinline__ float cgrad_stage(float2 (&f)[A], float2 (&l)[A], uint32_t (&pk)[(A + 3) / 4],
+                                             const float2* row, int cmin, float sc) {
+    opaque<A>(pk);
+    float a = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const int cq = static_cast<int>(cutv<A>(pk, r));
+        a = fmaf(static_cast<float>(cq + cmin), fmaf(l[r].x, f[r].y, -l[r].y * f[r].x), a);
+        if constexpr (UNDO) {
+            const float2 t0 = row[cq];
+            const float2 t = make_float2(sc * t0.x, sc * t0.y);
+            f[r] = cmulc(f[r], t);
+            l[r] = cmulc(l[r], t);
+        }
+        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    return a;
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// One full mixer layer on a state that sits in the layer's first stage.  Ascending
+// layers visit stages 0..S-1, descending ones S-1..0; a layer ends in the stage where
+// the next one (of the opposite direction) starts.
+template <int K, int G, bool DESC, int A>
+__device__ __forceinline__ void fwd_layer(float2 (&f)[A], float2* xb, uint32_t tau, float t) {
+    constexpr int S = Fz<K, G>::S;
+    static_for<0, S>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr int st = DESC ? S - 1 - j : j;
+        if constexpr (j > 0) {
+            constexpr int prev = DESC ? S - j : j - 1;
+            xpose<K, G, prev, st>(f, xb, tau);
+        }
+        mix_stage<K, G, st>(f, t);
+    });
+}
+
+// Undo a forward layer of direction DESC on psi and lambda (stages in reverse order);
+// returns the thread's share of Im <lambda| sum_j X_j |psi>.
+template <int K, int G, bool DESC, int A>
+__device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t,
+                                          float k2) {
+    constexpr int S = Fz<K, G>::S;
+    double acc = 0.0;
+    float w = 1.f;
+    static_for<0, S>([&](auto J) {
+        constexpr int j = decltype(J)::value;            // j-th stage of the reverse walk
+        constexpr int st = DESC ? j : S - 1 - j;
+        if constexpr (j > 0) {
+            constexpr int prev = DESC ? j - 1 : S - j;
+            xpose<K, G, prev, st>(f, xb, tau);
+            xpose<K, G, prev, st>(l, xb, tau);
+        }
+        acc += static_cast<double>(unmix_stage2<K, G, st>(f, l, t, k2, w));
+    });
+    return acc;
+}
+
+// Sum over the threads of one item (fixed order, identical result in every lane).
+template <int K, int G>
+__device__ __forceinline__ double item_sum(double x, double* red, int tid) {
+    using C = Fz<K, G>;
+    constexpr int seg = C::TPI < 64 ? C::TPI : 64;
+#pragma unroll
+    for (int o = 1; o < seg; o <<= 1) x += __shfl_xor(x, o, 64);
+    if constexpr (C::TPI > 64) {
+        constexpr int WPI = C::TPI / 64;
+        const int wave = tid >> 6;
+        __syncthreads();
+        if ((tid & 63) == 0) red[wave] = x;
+        __syncthreads();
+        const int w0 = (wave / WPI) * WPI;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < WPI; ++w) s += red[w0 + w];
+        x = s;
+    }
+    return x;
+}
+
+// ODD = (p - 1) is odd.  Layer l (1 <= l <= p-1) runs descending when p-1-l is even, so
+// layer p-1 ends in stage 0 (qubits 0 and 1).  With ODD the first layer is descending and
+// is peeled off; the remaining layers come in (ascending, descending) pairs, so no branch
+// ever selects between the two layer bodies.
+template <int K, bool GRAD, bool ODD>
+__global__ void __launch_bounds__((Fz<K, (GRAD ? 1 : 0)>::WG))
+k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
+        const uint8_t* __restrict__ cut_tables, int32_t rowcap, EvalArgs ea) {
+    constexpr int GI = GRAD ? 1 : 0;
+    using C = Fz<K, GI>;
+    constexpr int A = C::A;
+    __shared__ float2 xbuf[C::S > 1 ? C::IPW * C::NPAD : 1];
+    __shared__ __attribute__((aligned(16))) uint8_t cutl[C::IPW * C::N < 16 ? 16 : C::IPW * C::N];
+    __shared__ double red[C::WG / 64];
+    extern __shared__ float2 prow_all[];   // [IPW][p][rowcap] phase rows of every layer
+
+    const int tid = threadIdx.x;
+    const int il = tid >> C::TB;
+    const uint32_t tau = static_cast<uint32_t>(tid) & (C::TPI - 1);
+    int64_t item = item_base + static_cast<int64_t>(blockIdx.x) * C::IPW + il;
+    const bool valid = item < n_items;
+    if (!valid) item = n_items - 1;
+    const int P = ea.P, p = ea.p;
+    const int64_t slot = item / P;
+    const int point = static_cast<int>(item - slot * P);
+    const ConeDev cd = cones[slot];
+
+    {   // the cone's cut table -> LDS (each thread copies A bytes)
+        const uint8_t* src = cut_tables + cd.cut_off + static_cast<size_t>(tau) * A;
+        uint8_t* dst = cutl + il * C::N + tau * A;
+        if constexpr (A >= 16) {
+#pragma unroll
+            for (int j = 0; j < A; j += 16)
+                *reinterpret_cast<uint4*>(dst + j) = *reinterpret_cast<const uint4*>(src + j);
+        } else {
+#pragma unroll
+            for (int j = 0; j < A; ++j) dst[j] = src[j];
+        }
+    }
+    const uint8_t* cut = cutl + il * C::N;
+    float2* xb = xbuf + (C::S > 1 ? il * C::NPAD : 0);
+    const float2* phase0 = ea.phase + static_cast<size_t>(point) * p * ea.R + cd.cut_shift;
+    const float2* mix0 = ea.mix + static_cast<size_t>(point) * p;
+    {   // phase rows of every layer for this item: prow[il][l][c] = exp(-i gamma_l (cut_min + c))
+        float2* dst = prow_all + static_cast<size_t>(il) * p * rowcap;
+        for (int l = 0; l < p; ++l)
+            for (int c = static_cast<int>(tau); c < cd.cut_range; c += C::TPI)
+                dst[l * rowcap + c] = phase0[static_cast<size_t>(l) * ea.R + c];
+    }
+    const float2* rows = prow_all + static_cast<size_t>(il) * p * rowcap;
+    auto ROW = [&](int l) { return rows + l * rowcap; };
+    constexpr int SL = C::S - 1;
+    constexpr int NW = (A + 3) / 4;
+    __syncthreads();
+    uint32_t pk0[NW], pkL[NW];
+    load_cuts<K, GI, 0, A>(pk0, cut, tau);
+    load_cuts<K, GI, SL, A>(pkL, cut, tau);
+    // mix0[l] = (tau_l, |kappa_l|^2); a full factored layer scales the state by
+    // 1/|kappa|^K, the truncated last layer (qubits 0, 1) by 1/|kappa_p|^2.
+    auto kpowK = [&](float k2) { return exp2f(0.5f * K * log2f(k2)); };
+    const float k2p = mix0[p - 1].y;
+
+    float2 f[A];
+    // ---- D_1 |+>, then the full layers 1..p-1, each followed by the next phase.
+    // Phase row l (0-based) is scaled by the norm lost in the layer before it, and the
+    // last one also by |kappa_p|^2, so psi leaves the final mixer normalised.
+    {
+        const float sc = exp2f(-0.5f * K) * (p == 1 ? k2p : 1.f);
+        if constexpr (ODD) gen_stage(f, pkL, ROW(0), sc);
+        else gen_stage(f, pk0, ROW(0), sc);
+    }
+    int l1 = 1;
+    if constexpr (ODD) {
+        const float2 tk = mix0[0];
+        fwd_layer<K, GI, true>(f, xb, tau, tk.x);
+        phase_stage(f, pk0, ROW(1), kpowK(tk.y) * (p == 2 ? k2p : 1.f));
+        l1 = 2;
+    }
+    for (; l1 + 1 <= p - 1; l1 += 2) {
+        const float2 ta = mix0[l1 - 1];
+        fwd_layer<K, GI, false>(f, xb, tau, ta.x);
+        phase_stage(f, pkL, ROW(l1), kpowK(ta.y));
+        const float2 tb = mix0[l1];
+        fwd_layer<K, GI, true>(f, xb, tau, tb.x);
+        phase_stage(f, pk0, ROW(l1 + 1), kpowK(tb.y) * (l1 + 2 == p ? k2p : 1.f));
+    }
+
+    // ---- last layer: mixer on qubits 0, 1 (register bits 0, 1 of stage 0); <Z0 Z1>
+    const float tp = mix0[p - 1].x;
+#pragma unroll
+    for (int r = 0; r < A; ++r)
+        if (!(r & 1)) bfly(f[r], f[r | 1], tp);
+#pragma unroll
+    for (int r = 0; r < A; ++r)
+        if (!(r & 2)) bfly(f[r], f[r | 2], tp);
+    double zzp = 0.0;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const double pr = static_cast<double>(fmaf(f[r].x, f[r].x, f[r].y * f[r].y));
+        zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
+    }
+    const double zz = item_sum<K, GI>(zzp, red, tid);
+    if (valid && tau == 0) ea.zz[static_cast<size_t>(point) * ea.M + cd.orbit] = zz;
+
+    if constexpr (GRAD) {
+        const int M = ea.M;
+        double* gout = ea.g + static_cast<size_t>(point) * 2 * p * M + cd.orbit;
+        float2 lam[A];
+#pragma unroll
+        for (int r = 0; r < A; ++r) lam[r] = (((r ^ (r >> 1)) & 1) ? make_float2(-f[r].x, -f[r].y) : f[r]);
+        // d zz / d beta_p: only X_0, X_1 contribute in the truncated last layer
+        float acc = 0.f;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & 1)) acc += xterm(lam[r], lam[r | 1], f[r], f[r | 1]);
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & 2)) acc += xterm(lam[r], lam[r | 2], f[r], f[r | 2]);
+        const double gbp = item_sum<K, GI>(2.0 * static_cast<double>(acc), red, tid);
+        if (valid && tau == 0) gout[static_cast<size_t>(2 * p - 1) * M] = gbp;
+        // undo the last mixer: both states end up scaled by 1/|kappa_p|^2
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & 2)) { bfly(f[r], f[r | 2], -tp); bfly(lam[r], lam[r | 2], -tp); }
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & 1)) { bfly(f[r], f[r | 1], -tp); bfly(lam[r], lam[r | 1], -tp); }
+
+        // Walk the layers back.  Before the gamma_ly term both states carry the factor
+        // 1/mu_ly (mu_p = |kappa_p|^2, mu_ly = |kappa_ly|^K); D_ly is undone with a row
+        // scaled by mu_ly, which restores the true states.  Layer p-1 is descending, so
+        // undoing it ends in stage SL; the layers then alternate.
+        float mu = k2p;
+        int ly = p;
+        for (;;) {
+            if (ly == 1) {
+                const float a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
+                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                if (valid && tau == 0) gout[0] = gc;
+                break;
+            }
+            {
+                const float a = cgrad_stage<true>(f, lam, pk0, ROW(ly - 1), cd.cut_min, mu);
+                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
+            }
+            {
+                const float2 tk = mix0[ly - 2];
+                const double b = unlayer<K, GI, true>(f, lam, xb, tau, tk.x, tk.y);
+                const double gb = item_sum<K, GI>(2.0 * b, red, tid);
+                if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
+                mu = kpowK(tk.y);
+            }
+            --ly;
+            if (ly == 1) {
+                const float a = cgrad_stage<false>(f, lam, pkL, ROW(0), cd.cut_min, 1.f);
+                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                if (valid && tau == 0) gout[0] = gc;
+                break;
+            }
+            {
+                const float a = cgrad_stage<true>(f, lam, pkL, ROW(ly - 1), cd.cut_min, mu);
+                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
+            }
+            {
+                const float2 tk = mix0[ly - 2];
+                const double b = unlayer<K, GI, false>(f, lam, xb, tau, tk.x, tk.y);
+                const double gb = item_sum<K, GI>(2.0 * b, red, tid);
+                if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
+                mu = kpowK(tk.y);
+            }
+            --ly;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launcher
+template <int K>
+hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+                           const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
+    const int ipw = grad ? Fz<K, 1>::IPW : Fz<K, 0>::IPW;
+    const int wg = grad ? Fz<K, 1>::WG : Fz<K, 0>::WG;
+    const int64_t todo = n_items - item_base;
+    const int64_t blocks = (todo + ipw - 1) / ipw;
+    if (blocks <= 0) return hipSuccess;
+    const size_t dyn = static_cast<size_t>(ipw) * ea.p * rowcap * sizeof(float2);
+    const dim3 grid(static_cast<unsigned>(blocks)), block(wg);
+    const bool odd = ((ea.p - 1) & 1) != 0;
+    if (grad && odd)
+        hipLaunchKernelGGL((k_fused<K, true, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    else if (grad)
+        hipLaunchKernelGGL((k_fused<K, true, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    else if (odd)
+        hipLaunchKernelGGL((k_fused<K, false, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    else
+        hipLaunchKernelGGL((k_fused<K, false, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    return hipGetLastError();
+}
+
+}  // namespace qaoa

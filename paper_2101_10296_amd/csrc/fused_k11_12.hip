@@ -1,0 +1,16 @@
+// Instantiations of the workgroup-resident light-cone kernel (see fused_impl.hpp).
+#include "fused_impl.hpp"
+
+namespace qaoa {
+
+hipError_t launch_fused_k11(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+                          const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
+    return launch_k<11>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+}
+
+hipError_t launch_fused_k12(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+                          const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
+    return launch_k<12>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+}
+
+}  // namespace qaoa

@@ -1,0 +1,218 @@
+// Host planner (integer-exact).
+//
+//  * canonical edges: u < v, input order kept as the edge index; self-loops, duplicates
+//    and out-of-range ids rejected (MaxCut on a simple graph, Sec. 2.4)
+//  * generator check: a permutation of V mapping E onto E (automorphism, Sec. 2.6) that
+//    keeps every edge weight bit for bit (weighted symmetries, Sec. 4)
+//  * edge orbits by union-find over (e, sigma(e)) for every generator sigma and edge e;
+//    the class representative is its smallest edge index and classes are numbered by
+//    ascending representative (the paper lets the representative be arbitrary, Sec. 3)
+//  * one light cone per class: the radius-p ball around the representative's endpoints
+//    (reverse causal cone, Sec. 2.3) with u -> qubit 0, v -> qubit 1 and the rest ordered
+//    by (distance, node id); every edge induced on the ball is a cone edge
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace qaoa {
+namespace {
+
+[[noreturn]] void fail(int32_t st, const std::string& m) { throw PlanError{st, m}; }
+
+constexpr int32_t kEINVAL = -1, kENOTAUT = -2, kECONE = -3;
+
+// Sorted (key -> edge index) table for edge lookup by endpoints.
+struct EdgeIndex {
+    uint64_t n = 0;
+    std::vector<uint64_t> key;
+    std::vector<int64_t> idx;
+    void build(int32_t nn, const std::vector<int32_t>& u, const std::vector<int32_t>& v) {
+        n = static_cast<uint64_t>(nn);
+        const size_t m = u.size();
+        std::vector<std::pair<uint64_t, int64_t>> kv(m);
+        for (size_t i = 0; i < m; ++i) kv[i] = {static_cast<uint64_t>(u[i]) * n + static_cast<uint64_t>(v[i]), (int64_t)i};
+        std::sort(kv.begin(), kv.end());
+        key.resize(m);
+        idx.resize(m);
+        for (size_t i = 0; i < m; ++i) { key[i] = kv[i].first; idx[i] = kv[i].second; }
+    }
+    int64_t find(int32_t a, int32_t b) const {
+        if (a > b) std::swap(a, b);
+        const uint64_t k = static_cast<uint64_t>(a) * n + static_cast<uint64_t>(b);
+        auto it = std::lower_bound(key.begin(), key.end(), k);
+        if (it == key.end() || *it != k) return -1;
+        return idx[it - key.begin()];
+    }
+};
+
+// Union-find whose root is always the smallest index of its set.
+struct MinUnionFind {
+    std::vector<int64_t> parent;
+    explicit MinUnionFind(int64_t m) : parent(m) { for (int64_t i = 0; i < m; ++i) parent[i] = i; }
+    int64_t find(int64_t x) {
+        while (parent[x] != x) { parent[x] = parent[parent[x]]; x = parent[x]; }
+        return x;
+    }
+    void unite(int64_t a, int64_t b) {
+        a = find(a);
+        b = find(b);
+        if (a == b) return;
+        if (a < b) parent[b] = a; else parent[a] = b;
+    }
+};
+
+}  // namespace
+
+void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* ew,
+                     int32_t n_gen, const int32_t* gens, int32_t p, const PlanOptions& opt,
+                     HostPlan& P) {
+    if (n < 1) fail(kEINVAL, "n_nodes must be >= 1");
+    if (m < 0) fail(kEINVAL, "n_edges must be >= 0");
+    if (m > 0 && (!eu || !ev)) fail(kEINVAL, "edge arrays are NULL");
+    if (p < 1) fail(kEINVAL, "p must be >= 1");
+    if (n_gen < 0 || (n_gen > 0 && !gens)) fail(kEINVAL, "bad generator array");
+    if (opt.max_cone_qubits < 2 || opt.max_cone_qubits > 30) fail(kEINVAL, "max_cone_qubits must be in [2, 30]");
+    if (opt.k_lds_max < 2 || opt.k_lds_max > 14) fail(kEINVAL, "k_lds_max must be in [2, 14]");
+
+    P = HostPlan{};
+    P.n = n;
+    P.m = m;
+    P.p = p;
+    P.u.resize(m);
+    P.v.resize(m);
+    P.w.assign(m, 1.0);
+    P.unit = (ew == nullptr);
+    for (int64_t i = 0; i < m; ++i) {
+        int32_t a = eu[i], b = ev[i];
+        if (a < 0 || a >= n || b < 0 || b >= n) fail(kEINVAL, "edge " + std::to_string(i) + ": node id out of range");
+        if (a == b) fail(kEINVAL, "edge " + std::to_string(i) + ": self-loop");
+        if (a > b) std::swap(a, b);
+        P.u[i] = a;
+        P.v[i] = b;
+        if (ew) {
+            const double x = ew[i];
+            if (!std::isfinite(x)) fail(kEINVAL, "edge " + std::to_string(i) + ": non-finite weight");
+            if (x != std::floor(x) || std::fabs(x) > 16777216.0)
+                fail(kEINVAL, "edge " + std::to_string(i) + ": weights must be integers of magnitude <= 2^24");
+            P.w[i] = x;
+            if (x != 1.0) P.unit = false;
+        }
+    }
+    EdgeIndex index;
+    index.build(n, P.u, P.v);
+    for (int64_t i = 1; i < m; ++i)
+        if (index.key[i] == index.key[i - 1]) fail(kEINVAL, "duplicate edge (" + std::to_string(index.key[i] / index.n) + "," + std::to_string(index.key[i] % index.n) + ")");
+
+    // ---- generators: verify, then union every edge with its image
+    MinUnionFind uf(m);
+    std::vector<char> seen(n);
+    for (int32_t g = 0; g < n_gen; ++g) {
+        const int32_t* s = gens + static_cast<int64_t>(g) * n;
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int32_t i = 0; i < n; ++i) {
+            if (s[i] < 0 || s[i] >= n || seen[s[i]]) fail(kENOTAUT, "generator " + std::to_string(g) + " is not a permutation of the nodes");
+            seen[s[i]] = 1;
+        }
+        for (int64_t e = 0; e < m; ++e) {
+            const int64_t f = index.find(s[P.u[e]], s[P.v[e]]);
+            if (f < 0) fail(kENOTAUT, "generator " + std::to_string(g) + " maps edge " + std::to_string(e) + " to a non-edge");
+            if (std::memcmp(&P.w[e], &P.w[f], sizeof(double)) != 0)
+                fail(kENOTAUT, "generator " + std::to_string(g) + " does not preserve the weight of edge " + std::to_string(e));
+            if (opt.reduce) uf.unite(e, f);
+        }
+    }
+    P.edge_orbit.resize(m);
+    for (int64_t e = 0; e < m; ++e) {
+        const int64_t r = uf.find(e);
+        if (r == e) {
+            P.edge_orbit[e] = static_cast<int32_t>(P.rep.size());
+            P.rep.push_back(e);
+            P.size.push_back(0);
+            P.W.push_back(0.0);
+        } else {
+            P.edge_orbit[e] = P.edge_orbit[r];
+        }
+        P.size[P.edge_orbit[e]] += 1;
+        P.W[P.edge_orbit[e]] += P.w[e];
+        P.total_weight += P.w[e];
+    }
+
+    // ---- CSR adjacency with edge ids
+    std::vector<int64_t> off(static_cast<size_t>(n) + 1, 0);
+    for (int64_t e = 0; e < m; ++e) { off[P.u[e] + 1]++; off[P.v[e] + 1]++; }
+    for (int32_t i = 0; i < n; ++i) off[i + 1] += off[i];
+    std::vector<int32_t> nbr(2 * m);
+    std::vector<int64_t> nbr_e(2 * m);
+    {
+        std::vector<int64_t> pos(off.begin(), off.end() - 1);
+        for (int64_t e = 0; e < m; ++e) {
+            nbr[pos[P.u[e]]] = P.v[e]; nbr_e[pos[P.u[e]]++] = e;
+            nbr[pos[P.v[e]]] = P.u[e]; nbr_e[pos[P.v[e]]++] = e;
+        }
+    }
+
+    // ---- light cones
+    const int32_t kmax = opt.max_cone_qubits;
+    std::vector<int32_t> mark(n, -1), dist(n, 0), loc(n, -1);
+    P.cones.resize(P.rep.size());
+    P.cut_min = 0;
+    P.cut_max = 0;
+    for (size_t o = 0; o < P.rep.size(); ++o) {
+        const int64_t e0 = P.rep[o];
+        const int32_t a0 = P.u[e0], b0 = P.v[e0];
+        const int32_t stamp = static_cast<int32_t>(o);
+        std::vector<int32_t> ball{a0, b0};
+        mark[a0] = mark[b0] = stamp;
+        dist[a0] = dist[b0] = 0;
+        size_t lo = 0;
+        for (int32_t d = 1; d <= p; ++d) {
+            const size_t hi = ball.size();
+            for (size_t t = lo; t < hi; ++t) {
+                const int32_t x = ball[t];
+                for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+                    const int32_t y = nbr[j];
+                    if (mark[y] != stamp) {
+                        mark[y] = stamp;
+                        dist[y] = d;
+                        ball.push_back(y);
+                        if (static_cast<int32_t>(ball.size()) > kmax)
+                            fail(kECONE, "light cone of orbit " + std::to_string(o) + " (edge " + std::to_string(e0) +
+                                         ") exceeds " + std::to_string(kmax) + " qubits");
+                    }
+                }
+            }
+            lo = hi;
+        }
+        std::sort(ball.begin() + 2, ball.end(), [&](int32_t x, int32_t y) {
+            return dist[x] != dist[y] ? dist[x] < dist[y] : x < y;
+        });
+        Cone& c = P.cones[o];
+        c.k = static_cast<int32_t>(ball.size());
+        c.nodes = ball;
+        for (int32_t i = 0; i < c.k; ++i) loc[ball[i]] = i;
+        int64_t cmin = 0, cmax = 0;
+        for (int32_t i = 0; i < c.k; ++i) {
+            const int32_t x = ball[i];
+            for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+                const int32_t y = nbr[j];
+                if (mark[y] == stamp && loc[y] > i) {
+                    c.ea.push_back(i);
+                    c.eb.push_back(loc[y]);
+                    const int32_t wi = static_cast<int32_t>(P.w[nbr_e[j]]);
+                    c.ew.push_back(wi);
+                    if (wi < 0) cmin += wi; else cmax += wi;
+                }
+            }
+        }
+        if (cmax - cmin > 255)
+            fail(kECONE, "cut values of the cone of orbit " + std::to_string(o) + " span more than 255 integers");
+        c.cut_min = static_cast<int32_t>(cmin);
+        c.cut_max = static_cast<int32_t>(cmax);
+        P.cut_min = std::min<int32_t>(P.cut_min, c.cut_min);
+        P.cut_max = std::max<int32_t>(P.cut_max, c.cut_max);
+    }
+}
+
+}  // namespace qaoa

@@ -1,0 +1,54 @@
+// Host planner: graph canonicalisation, generator verification, edge orbits and
+// light-cone extraction.  Integer-exact; no device code.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qaoa {
+
+struct PlanError {
+    int32_t status;
+    std::string msg;
+};
+
+// One light cone: the subgraph induced by the radius-p ball around an edge (Sec. 2.3).
+struct Cone {
+    int32_t k = 0;                         // qubits
+    std::vector<int32_t> nodes;            // graph node of each qubit (u, v, then by (dist, id))
+    std::vector<int32_t> ea, eb;           // induced edges as qubit pairs, ea < eb
+    std::vector<int32_t> ew;               // integer weight of each induced edge
+    int32_t cut_min = 0, cut_max = 0;      // range of the cut value C(x) over all x
+};
+
+struct HostPlan {
+    int32_t n = 0, p = 0;
+    int64_t m = 0;
+    std::vector<int32_t> u, v;             // canonical edges, u < v, input order
+    std::vector<double> w;                 // weights (1.0 when unit)
+    bool unit = true;
+    std::vector<int32_t> edge_orbit;       // [m]
+    std::vector<int64_t> rep, size;        // [M]
+    std::vector<double> W;                 // [M] orbit weight = sum of member weights
+    std::vector<Cone> cones;               // [M]
+    double total_weight = 0.0;
+    int32_t cut_min = 0, cut_max = 0;      // over all cones
+};
+
+struct PlanOptions {
+    int64_t mem_budget_bytes = 0;
+    int32_t reduce = 1;
+    int32_t max_cone_qubits = 30;
+    int32_t k_lds_max = 14;
+    int32_t checkpoint_mode = 0;
+    int32_t one_cone_at_a_time = 0;
+    int32_t profile = 0;
+};
+
+// Throws PlanError on invalid input.
+void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* ew,
+                     int32_t n_gen, const int32_t* gens, int32_t p, const PlanOptions& opt,
+                     HostPlan& out);
+
+}  // namespace qaoa

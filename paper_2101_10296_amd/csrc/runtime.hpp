@@ -1,0 +1,69 @@
+// Per-plan device state and the energy driver behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "plan.hpp"
+#include "qaoa.h"
+
+struct qaoa_plan_s {
+    qaoa::HostPlan hp;
+    qaoa::PlanOptions opt;
+
+    // ---- device-resident plan data (built on the first energy call)
+    int device = -1;
+    bool dev_ready = false;
+    struct Group {
+        int K;          // cone qubits
+        int64_t first;  // first slot in d_cones
+        int64_t count;  // cones in this group
+        int32_t rowcap; // largest cut range of the group's cones
+    };
+    std::vector<Group> lds_groups;      // workgroup-resident cones, grouped by K
+    qaoa::ConeDev* d_cones = nullptr;
+    uint8_t* d_cut = nullptr;
+    double* d_W = nullptr;
+    size_t resident_bytes = 0;
+
+    // ---- profiling (opts.profile): events around each kernel group of the last call
+    struct Timed {
+        int32_t k;
+        int64_t items;
+        hipEvent_t start, stop;
+    };
+    std::vector<Timed> timed;
+    size_t n_timed = 0;
+
+    // ---- per-call scratch, grown on demand
+    size_t cap_phase = 0, cap_mix = 0, cap_zz = 0, cap_g = 0;
+    float2* d_phase = nullptr;
+    float2* d_mix = nullptr;
+    double* d_zz = nullptr;
+    double* d_g = nullptr;
+};
+
+namespace qaoa {
+
+qaoa_status run_energy(qaoa_plan_s* plan, int64_t n_points, const double* gamma, const double* beta,
+                       double* energy, double* term_zz, double* dgamma, double* dbeta, hipStream_t stream,
+                       std::string& msg);
+
+void release_device(qaoa_plan_s* plan);
+qaoa_status kernel_times(qaoa_plan_s* plan, int32_t cap, int32_t* k_out, int64_t* items_out, double* ms_out,
+                         int32_t* n_out, std::string& msg);
+
+// kernel launchers
+hipError_t launch_fused(int K, bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+                        const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st);
+hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, int32_t R, int32_t cmin,
+                         float2* phase, float2* mix, hipStream_t st);
+hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
+                             const int32_t* ew, uint8_t* tables, hipStream_t st);
+hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
+                          double* energy, double* dgamma, double* dbeta, hipStream_t st);
+
+}  // namespace qaoa

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (FP32 amplitudes, FP64 accumulation):
+  * per term       |zz_gpu - zz_oracle| <= 1e-5
+  * energy         |E_gpu - E_oracle|  <= 1e-5 * W_total / 2   (E = sum_m W_m (1 - zz_m) / 2)
+  * gradient       ||g_gpu - g_oracle||_inf <= 1e-4 * max(||g_oracle||_inf, 1e-3 * W_total) per point
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ZZ_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2101_10296_amd as Q
+    return Q
+
+
+def dev(a):
+    return torch.as_tensor(np.asarray(a, np.float64), device="cuda")
+
+
+def check_energy(Q, g, p, ga, be, reduce=True, weights=None, grad=False, plan_kw=None, sample=None):
+    plan_kw = plan_kw or {}
+    pl = Q.Plan(g.n, g.edges, p=p, weights=weights, generators=g.gens() if reduce else None, reduce=reduce,
+                **plan_kw)
+    ref = oracle.plan(g.n, g.edges, weights, g.gens() if reduce else None, p, reduce=reduce, max_k=30)
+    E, zz = pl.energy(dev(ga), dev(be), term_zz=True)
+    torch.cuda.synchronize()
+    E, zz = E.cpu().numpy(), zz.cpu().numpy()
+    Wt = float(np.sum(ref["W"]))
+    if sample is None:
+        Eo, zzo = oracle.energy(ref, ga, be)
+        assert np.abs(zz - zzo).max() <= ZZ_TOL, np.abs(zz - zzo).max()
+        assert np.abs(E - Eo).max() <= ZZ_TOL * Wt / 2 + 1e-12
+    else:   # sampled terms (large plans): oracle term by term
+        rng = np.random.default_rng(0)
+        ms = rng.choice(len(ref["rep"]), size=min(sample, len(ref["rep"])), replace=False)
+        sub = dict(ref, cones=[ref["cones"][m] for m in ms], rep=ref["rep"][ms], W=ref["W"][ms])
+        _, zzo = oracle.energy(sub, ga, be)
+        assert np.abs(zz[:, ms] - zzo).max() <= ZZ_TOL
+        # the energy is the orbit-weighted sum of the GPU's own terms
+        np.testing.assert_allclose(E, (ref["W"][None, :] * (1 - zz) / 2).sum(1), rtol=1e-12, atol=1e-9)
+    if grad:
+        E2, dg, db = pl.energy_grad(dev(ga), dev(be))
+        torch.cuda.synchronize()
+        # the adjoint kernels use their own register layout, so E agrees to rounding only
+        assert np.abs(E2.cpu().numpy() - E).max() <= ZZ_TOL * Wt / 2 + 1e-12
+        Eo, dgo, dbo, _ = oracle.energy_grad(ref, ga, be)
+        dg, db = dg.cpu().numpy(), db.cpu().numpy()
+        for i in range(ga.shape[0]):
+            ref_inf = max(np.abs(dgo[i]).max(), np.abs(dbo[i]).max())
+            err = max(np.abs(dg[i] - dgo[i]).max(), np.abs(db[i] - dbo[i]).max())
+            assert err <= 1e-4 * max(ref_inf, 1e-3 * Wt), (i, err, ref_inf)
+    return pl, E, zz
+
+
+def test_config1_n16_p1(Q):
+    (g, p), = W.workload("c1")[0]
+    _, ga, be = W.workload("c1")
+    pl, E, zz = check_energy(Q, g, p, ga, be, reduce=False, grad=True)
+    Eb, zzb = oracle.bruteforce_full(g.n, g.edges, None, ga[0], be[0])
+    assert abs(E[0] - Eb) <= ZZ_TOL * g.m / 2
+    cf = [oracle.zz_p1(g.n, g.edges, None, int(a), int(b), ga[0, 0], be[0, 0]) for a, b in g.edges]
+    assert np.abs(zz[0] - np.array(cf)).max() <= ZZ_TOL
+
+
+def test_single_edge_and_triangle(Q):
+    ga, be = W.draw_angles(7, 1, 3)
+    check_energy(Q, W.single_edge(), 1, ga, be, grad=True)
+    check_energy(Q, W.triangle(), 1, ga, be, grad=True)
+    ga, be = W.draw_angles(5, 2, 4)
+    check_energy(Q, W.triangle(), 2, ga, be, grad=True)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_random_regular_small(Q, p):
+    g = W.random_regular(12, 3, 31)
+    ga, be = W.draw_angles(9, p, 10 + p)
+    check_energy(Q, g, p, ga, be, reduce=False, grad=True)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_every_workgroup_cone_size(Q, p):
+    # star K_{1,m}: every cone is the whole star, k = m + 1 = 2 .. 14 qubits
+    for m in range(1, 14):
+        g = W.star(m)
+        ga, be = W.draw_angles(3, p, 50 + m)
+        pl, _, _ = check_energy(Q, g, p, ga, be, reduce=(m % 2 == 0), grad=True)
+        assert pl.info()["max_k"] == m + 1
+
+
+def test_mixed_cone_sizes_one_plan(Q):
+    g = W.random_regular(40, 3, 7)
+    ga, be = W.draw_angles(6, 2, 77)
+    pl, _, _ = check_energy(Q, g, 2, ga, be, reduce=False, grad=True)
+    assert len([c for c in pl.info()["k_hist"] if c]) >= 3
+
+
+def test_reduced_equals_unreduced_and_theorem1(Q):
+    g = W.circulant(50, (1, 2))
+    ga, be = W.draw_angles(11, 2, 7)
+    pr = Q.Plan(g.n, g.edges, p=2, generators=g.gens())
+    pu = Q.Plan(g.n, g.edges, p=2, reduce=False)
+    Er, zr = pr.energy(dev(ga), dev(be), term_zz=True)
+    Eu, zu = pu.energy(dev(ga), dev(be), term_zz=True)
+    eo, rep, _ = pr.orbits()
+    zu, zr = zu.cpu().numpy(), zr.cpu().numpy()
+    # Theorem 1 on the GPU's own unreduced terms (FP32 rounding only)
+    for m in range(len(rep)):
+        assert np.abs(zu[:, eo == m] - zr[:, m:m + 1]).max() <= 1e-6
+    np.testing.assert_allclose(Er.cpu().numpy(), Eu.cpu().numpy(), rtol=1e-6)
+
+
+def test_weighted_integer(Q):
+    rng = np.random.default_rng(5)
+    g = W.random_regular(14, 3, 9)
+    w = rng.choice([-1.0, 1.0, 2.0], size=g.m)
+    ga, be = W.draw_angles(4, 2, 12)
+    check_energy(Q, g, 2, ga, be, reduce=False, weights=w, grad=True)
+
+
+def test_angle_edge_cases(Q):
+    g = W.random_regular(16, 3, 4)
+    ga = np.array([[0.0, 0.3], [1.1, 0.0], [np.pi / 2, np.pi], [-0.7, 2.9], [7.0, -4.0]])
+    be = np.array([[0.2, 0.0], [0.0, 0.0], [np.pi / 4, np.pi / 4], [np.pi / 2, -0.1], [3.0, 1.0]])
+    check_energy(Q, g, 2, ga, be, reduce=False, grad=True)
+
+
+def test_deterministic_and_plain_path_identical(Q):
+    g = W.random_regular(60, 3, 8)
+    ga, be = W.draw_angles(5, 2, 1)
+    pl = Q.Plan(g.n, g.edges, p=2)
+    E1, dg1, db1 = pl.energy_grad(dev(ga), dev(be))
+    E2, dg2, db2 = pl.energy_grad(dev(ga), dev(be))
+    plain = Q.Plan(g.n, g.edges, p=2, one_cone_at_a_time=True)
+    E3, dg3, db3 = plain.energy_grad(dev(ga), dev(be))
+    for a, b, c in ((E1, E2, E3), (dg1, dg2, dg3), (db1, db2, db3)):
+        assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_ragged_batches(Q):
+    g = W.random_regular(20, 3, 3)
+    pl = Q.Plan(g.n, g.edges, p=2)
+    ref = oracle.plan(g.n, g.edges, None, None, 2)
+    for P in (1, 3, 63, 65, 130):
+        ga, be = W.draw_angles(P, 2, P)
+        E = pl.energy(dev(ga), dev(be)).cpu().numpy()
+        Eo, _ = oracle.energy(ref, ga, be)
+        assert np.abs(E - Eo).max() <= ZZ_TOL * g.m / 2
+
+
+def test_autograd_function(Q):
+    g = W.circulant(40, (1, 2))
+    pl = Q.Plan(g.n, g.edges, p=2, generators=g.gens())
+    ga, be = W.draw_angles(3, 2, 2)
+    gt = dev(ga).requires_grad_(True)
+    bt = dev(be).requires_grad_(True)
+    E = Q.qaoa_energy(pl, gt, bt)
+    wts = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
+    (E * wts).sum().backward()
+    _, dg, db = pl.energy_grad(dev(ga), dev(be))
+    torch.testing.assert_close(gt.grad, dg * wts[:, None])
+    torch.testing.assert_close(bt.grad, db * wts[:, None])
+
+
+def test_config2_circulant_reduced(Q):
+    (g, p), = W.workload("c2i")[0]
+    _, ga, be = W.workload("c2i")
+    check_energy(Q, g, p, ga[:32], be[:32], grad=True)
+
+
+def test_config3_full_gradient_one_point(Q):
+    # random 3-regular n=1000, p=2: every one of the 1500 cone gradients at one angle point
+    (g, p), = W.workload("c3")[0]
+    _, ga, be = W.workload("c3")
+    check_energy(Q, g, p, ga[:1], be[:1], grad=True)
+
+
+def test_config2ii_full_batch_sampled_terms(Q):
+    # the bench workload at its full size (15000 cones x 256 points), 40 terms checked
+    (g, p), = W.workload("c2ii")[0]
+    _, ga, be = W.workload("c2ii")
+    pl, E, zz = check_energy(Q, g, p, ga, be, sample=40)
+    E2, dg, db = pl.energy_grad(dev(ga), dev(be))
+    assert np.abs(E2.cpu().numpy() - E).max() <= ZZ_TOL * g.m / 2
+    assert torch.isfinite(dg).all() and torch.isfinite(db).all()
+
+
+def test_input_errors(Q):
+    g = W.random_regular(12, 3, 1)
+    pl = Q.Plan(g.n, g.edges, p=2)
+    with pytest.raises(ValueError):
+        pl.energy(dev(np.zeros((2, 2))), dev(np.zeros((3, 2))))

@@ -16,6 +16,7 @@ from .graphs import (  # noqa: F401
     paley,
     triangle,
     single_edge,
+    star,
     relabel,
 )
 from .angles import draw_angles  # noqa: F401

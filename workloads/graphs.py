@@ -18,6 +18,7 @@ Families and the generators they carry:
 * complete graph K_n: the transposition (0 1) and the n-cycle
 * rook graph K_n x K_n: row transposition, row cycle and the transpose (i, j) -> (j, i)
 * Paley graph on a prime q = 1 (mod 4): x -> x+1 and x -> g^2 x (g a primitive root)
+* star K_{1,m}: a transposition and a cycle of the leaves
 """
 from __future__ import annotations
 
@@ -190,6 +191,20 @@ def paley(q: int) -> Graph:
     x = np.arange(q)
     return Graph(f"paley{q}", q, _canon(q, np.stack([a[keep], b[keep]], 1)),
                  generators=np.stack([(x + 1) % q, (g * g * x) % q]).astype(np.int32))
+
+
+def star(m: int) -> Graph:
+    """Star K_{1,m}: hub 0 joined to leaves 1..m; generators permute the leaves."""
+    e = np.stack([np.zeros(m, np.int64), np.arange(1, m + 1)], 1)
+    n = m + 1
+    i = np.arange(n)
+    gens = []
+    if m >= 2:
+        t = i.copy()
+        t[1], t[2] = 2, 1
+        cyc = np.where(i == 0, 0, (i % m) + 1)
+        gens = [t, cyc]
+    return Graph(f"star{m}", n, _canon(n, e), generators=np.asarray(gens, np.int32).reshape(-1, n))
 
 
 def single_edge() -> Graph:
