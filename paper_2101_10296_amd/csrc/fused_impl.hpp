@@ -81,9 +81,24 @@ __device__ __forceinline__ void bfly(float2& a, float2& b, float t) {
     b.y = fmaf(-t, a0.x, b0.y);
 }
 
-// Im(conj(la) pb) + Im(conj(lb) pa): the pair's share of Im <lambda| X_j |psi>.
-__device__ __forceinline__ float xterm(float2 la, float2 lb, float2 pa, float2 pb) {
-    return fmaf(la.x, pb.y, -la.y * pb.x) + fmaf(lb.x, pa.y, -lb.y * pa.x);
+// Accumulations into a single register are written as in-order FMAs.  Left to itself the
+// compiler defers such a dependent chain past the following butterflies and then has to
+// keep whole earlier generations of both states alive (hundreds of registers); pinning
+// the chain next to the butterfly that produced its inputs keeps the states in place.
+// acc += Im(conj(la) pb) + Im(conj(lb) pa)
+__device__ __forceinline__ void xacc(float& acc, float2 la, float2 lb, float2 pa, float2 pb) {
+    asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "v"(la.x), "v"(pb.y));
+    asm volatile("v_fma_f32 %0, -%1, %2, %0" : "+v"(acc) : "v"(la.y), "v"(pb.x));
+    asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "v"(lb.x), "v"(pa.y));
+    asm volatile("v_fma_f32 %0, -%1, %2, %0" : "+v"(acc) : "v"(lb.y), "v"(pa.x));
+}
+
+// acc += c * Im(conj(l) f)
+__device__ __forceinline__ void cacc(float& acc, float c, float2 l, float2 f) {
+    float im;
+    asm volatile("v_mul_f32 %0, %1, %2" : "=v"(im) : "v"(l.x), "v"(f.y));
+    asm volatile("v_fma_f32 %0, -%1, %2, %0" : "+v"(im) : "v"(l.y), "v"(f.x));
+    asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "v"(c), "v"(im));
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -130,8 +145,8 @@ __device__ __forceinline__ float unmix_stage2(float2 (&f)[A], float2 (&l)[A], fl
                 const int r2 = r | (1 << i);
                 bfly(f[r], f[r2], -t);
                 bfly(l[r], l[r2], -t);
-                if (np++ & 1) a1 += xterm(l[r], l[r2], f[r], f[r2]);
-                else a0 += xterm(l[r], l[r2], f[r], f[r2]);
+                if (np++ & 1) xacc(a1, l[r], l[r2], f[r], f[r2]);
+                else xacc(a0, l[r], l[r2], f[r], f[r2]);
                 if ((np & 3) == 0) __builtin_amdgcn_sched_barrier(0);
             }
         w *= k2;
@@ -220,7 +235,7 @@ __device__ __forceinline__ float cgrad_stage(float2 (&f)[A], float2 (&l)[A], uin
 #pragma unroll
     for (int r = 0; r < A; ++r) {
         const int cq = static_cast<int>(cutv<A>(pk, r));
-        a = fmaf(static_cast<float>(cq + cmin), fmaf(l[r].x, f[r].y, -l[r].y * f[r].x), a);
+        cacc(a, static_cast<float>(cq + cmin), l[r], f[r]);
         if constexpr (UNDO) {
             const float2 t0 = row[cq];
             const float2 t = make_float2(sc * t0.x, sc * t0.y);
@@ -414,10 +429,10 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         float acc = 0.f;
 #pragma unroll
         for (int r = 0; r < A; ++r)
-            if (!(r & 1)) acc += xterm(lam[r], lam[r | 1], f[r], f[r | 1]);
+            if (!(r & 1)) xacc(acc, lam[r], lam[r | 1], f[r], f[r | 1]);
 #pragma unroll
         for (int r = 0; r < A; ++r)
-            if (!(r & 2)) acc += xterm(lam[r], lam[r | 2], f[r], f[r | 2]);
+            if (!(r & 2)) xacc(acc, lam[r], lam[r | 2], f[r], f[r | 2]);
         const double gbp = item_sum<K, GI>(2.0 * static_cast<double>(acc), red, tid);
         if (valid && tau == 0) gout[static_cast<size_t>(2 * p - 1) * M] = gbp;
         // undo the last mixer: both states end up scaled by 1/|kappa_p|^2
