@@ -77,8 +77,9 @@ typedef struct {
     int32_t reduce;               /* 1 = one term per edge orbit (default); 0 = every edge is
                                      its own term (the plain, unreduced light-cone sum) */
     int32_t max_cone_qubits;      /* 0 = 30 */
-    int32_t k_lds_max;            /* cones with k <= this run entirely inside one workgroup
-                                     (0 = default 14, at most 14) */
+    int32_t k_lds_max;            /* cones with k <= this run entirely inside one workgroup,
+                                     larger ones as passes over tiles held in device memory
+                                     (0 = default 14; 13 or 14) */
     int32_t checkpoint_mode;      /* adjoint of cones held in HBM: 0 = uncompute (default:
                                      the forward state is recovered by inverse layers),
                                      1 = keep one state per pass when it fits the budget */

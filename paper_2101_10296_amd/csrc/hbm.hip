@@ -1,0 +1,117 @@
+// Launchers of the HBM-resident pass kernels, their per-plan tables and reductions.
+#include "hbm_impl.hpp"
+
+namespace qaoa {
+
+// C_tt table of (cone, group): for every tile index q, the weighted cut of the cone edges
+// whose two ends lie inside the tile, minus tt_min, as a byte.
+__global__ void k_tt_tables(const ConeHbm* __restrict__ cones, const int32_t* __restrict__ ea,
+                            const int32_t* __restrict__ eb, const int32_t* __restrict__ ew,
+                            uint8_t* __restrict__ tt) {
+    const ConeHbm cd = cones[blockIdx.x];
+    const int grp = blockIdx.y;
+    if (grp >= cd.n_groups) return;
+    __shared__ int32_t pos[32];   // tile position of each global bit, -1 if outer
+    if (threadIdx.x < 32) pos[threadIdx.x] = -1;
+    __syncthreads();
+    if (threadIdx.x < HT) {
+        int h;
+        pos[hgroup_bits(cd.k, grp, threadIdx.x, h)] = threadIdx.x;
+    }
+    __syncthreads();
+    uint8_t* out = tt + cones[blockIdx.x].tt_off[grp];
+    const int32_t tmin = cones[blockIdx.x].tt_min[grp];
+    for (uint32_t q = threadIdx.x; q < HN; q += blockDim.x) {
+        int32_t c = 0;
+        for (int e = 0; e < cd.n_edges; ++e) {
+            const int pa = pos[ea[cd.edge_off + e]], pb = pos[eb[cd.edge_off + e]];
+            if (pa >= 0 && pb >= 0) c += ew[cd.edge_off + e] * static_cast<int32_t>(((q >> pa) ^ (q >> pb)) & 1u);
+        }
+        out[q] = static_cast<uint8_t>(c - tmin);
+    }
+}
+
+__global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        x[i] = 0.0;
+}
+
+// Per item: fixed-order sum over tiles of the partial sums (stride values per tile);
+// j = 0 -> zz, j >= 1 -> d zz.
+__global__ void __launch_bounds__(256)
+k_tile_reduce(const ConeHbm* __restrict__ cones, const double* __restrict__ gpart, int64_t item0, int64_t tiles,
+              int32_t stride, EvalArgs ea) {
+    __shared__ double sh[256];
+    const int64_t bslot = blockIdx.x;
+    const int j = blockIdx.y;
+    const int64_t item = item0 + bslot;
+    const int64_t cslot = item / ea.P;
+    const int point = static_cast<int>(item - cslot * ea.P);
+    const int orbit = cones[cslot].orbit;
+    const double* src = gpart + static_cast<size_t>(bslot) * tiles * stride + j;
+    double acc = 0.0;
+    for (int64_t t = threadIdx.x; t < tiles; t += 256) acc += src[t * stride];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (j == 0) ea.zz[static_cast<size_t>(point) * ea.M + orbit] = sh[0];
+        else ea.g[(static_cast<size_t>(point) * 2 * ea.p + (j - 1)) * ea.M + orbit] = sh[0];
+    }
+}
+
+template <int KIND, bool G0>
+static hipError_t launch_one(const PassArgs& pa, hipStream_t st) {
+    constexpr bool GR = KIND >= GR_GEN_FINAL;
+    const int64_t tiles = int64_t{1} << (pa.k - HT);
+    const int64_t blocks = tiles * pa.n_batch;
+    const size_t dyn = static_cast<size_t>(pa.ea.p) * pa.rowcap * sizeof(float2);
+    hipLaunchKernelGGL((k_pass<KIND, G0>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<GR>::W), dyn, st, pa);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(int kind, const PassArgs& pa, hipStream_t st) {
+    const bool g0 = pa.group == 0;
+    switch (kind) {
+        case FWD_GEN_MIX: return g0 ? launch_one<FWD_GEN_MIX, true>(pa, st) : launch_one<FWD_GEN_MIX, false>(pa, st);
+        case FWD_GEN_FINAL: return g0 ? launch_one<FWD_GEN_FINAL, true>(pa, st) : hipErrorInvalidValue;
+        case FWD_MIX: return g0 ? launch_one<FWD_MIX, true>(pa, st) : launch_one<FWD_MIX, false>(pa, st);
+        case FWD_BND_MIX: return g0 ? launch_one<FWD_BND_MIX, true>(pa, st) : launch_one<FWD_BND_MIX, false>(pa, st);
+        case FWD_BND_FINAL: return g0 ? launch_one<FWD_BND_FINAL, true>(pa, st) : hipErrorInvalidValue;
+        case GR_GEN_FINAL: return g0 ? launch_one<GR_GEN_FINAL, true>(pa, st) : hipErrorInvalidValue;
+        case GR_BND_FINAL: return g0 ? launch_one<GR_BND_FINAL, true>(pa, st) : hipErrorInvalidValue;
+        case RV_GEN_MIX: return g0 ? launch_one<RV_GEN_MIX, true>(pa, st) : launch_one<RV_GEN_MIX, false>(pa, st);
+        case RV_MIX: return g0 ? launch_one<RV_MIX, true>(pa, st) : launch_one<RV_MIX, false>(pa, st);
+        case RV_BND_MIX: return g0 ? launch_one<RV_BND_MIX, true>(pa, st) : launch_one<RV_BND_MIX, false>(pa, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tt_tables(const ConeHbm* cones, int64_t n_cones, int max_groups, const int32_t* ea,
+                            const int32_t* eb, const int32_t* ew, uint8_t* tt, hipStream_t st) {
+    if (n_cones <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tt_tables, dim3(static_cast<unsigned>(n_cones), static_cast<unsigned>(max_groups)),
+                       dim3(256), 0, st, cones, ea, eb, ew, tt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* x, int64_t n, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_zero, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_reduce(const ConeHbm* cones, const double* gpart, int64_t item0, int64_t n_batch,
+                              int64_t tiles, int32_t stride, int32_t nvals, const EvalArgs& ea, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_reduce, dim3(static_cast<unsigned>(n_batch), static_cast<unsigned>(nvals)), dim3(256),
+                       0, st, cones, gpart, item0, tiles, stride, ea);
+    return hipGetLastError();
+}
+
+}  // namespace qaoa

@@ -1,0 +1,515 @@
+// HBM-resident light cones (more qubits than one workgroup holds): the state of each
+// (cone, angle point) item lives in device memory and every layer is applied by passes
+// over tiles of 2^13 amplitudes.
+//
+// A pass works on one pass group of qubits.  Group 0 holds qubits 0..12 (so qubits 0 and
+// 1, u and v, for the final mixer and <Z0 Z1>); group j >= 1 holds up to nine of the
+// remaining qubits, 13 + 9(j-1) .. , and carries global bits 0..3 so that every row of a
+// tile is 16 contiguous amplitudes (128 bytes).  Tile bits map to global bits through
+// gmap; the bits outside the tile select the tile.
+//
+// Layer order (the forward program, built on the host): layers alternate the order in
+// which they visit the groups, so that the last group of layer l is the first group of
+// layer l+1 and one pass does "finish layer l on this group, phase l+1, start layer l+1
+// on this group".  Layer p-1 ends on group 0, whose pass also applies the last phase,
+// the mixer on qubits 0 and 1 and <Z0 Z1>.  The adjoint runs the passes backwards,
+// undoing the forward operations on psi (read back from the state buffer, which holds the
+// forward input of the pass being undone, or recovered by inverse layers) and lambda.
+//
+// Inside a tile the amplitudes sit in registers in rotated layouts, exactly as in the
+// workgroup-resident kernel (fused_impl.hpp), with LDS transposes between layouts; an
+// extra I/O layout puts lanes on the contiguous global bits for coalesced loads/stores.
+// The cut value of a basis state x = (outer bits o, tile bits q) is
+//   C(x) = C_oo(o) + sum_b W1_b(o) + sum_b q_b (WO_b - 2 W1_b(o)) + C_tt(q),
+// where b runs over tile bits, WO_b / W1_b are the weights of b's edges to outer bits
+// (all of them / those whose outer end is 1 in o), and C_tt is a per-(cone, group) table.
+#pragma once
+
+#include "fused_impl.hpp"
+
+namespace qaoa {
+
+constexpr int HT = 13;                 // tile bits
+constexpr uint32_t HN = 1u << HT;      // amplitudes per tile
+
+// Pass kinds.  FWD_* are forward passes; GR_* fuse the final forward pass with the start
+// of the adjoint; RV_* undo a forward pass on (psi, lambda).
+enum PassKind : int {
+    FWD_GEN_MIX = 0,   // D_1 |+>, mixer of layer 1 on the group, store
+    FWD_GEN_FINAL,     // p = 1: D_1 |+>, mixer on qubits 0, 1, <Z0 Z1>
+    FWD_MIX,           // load, mixer of layer la, store
+    FWD_BND_MIX,       // load, mixer la, phase lb = la + 1, mixer lb, store
+    FWD_BND_FINAL,     // load, mixer la = p - 1, phase p, last mixer, <Z0 Z1>
+    GR_GEN_FINAL,      // p = 1 forward + adjoint, no state buffers
+    GR_BND_FINAL,      // FWD_BND_FINAL + adjoint turn: store lambda at the pass input
+    RV_GEN_MIX,        // undo FWD_GEN_MIX (gradients of beta_1 share, gamma_1)
+    RV_MIX,            // undo FWD_MIX, store psi and lambda
+    RV_BND_MIX,        // undo FWD_BND_MIX, store psi and lambda
+    N_PASS_KINDS
+};
+
+// One HBM-class light cone.
+struct ConeHbm {
+    int32_t orbit;
+    int32_t k;
+    int32_t edge_off;
+    int32_t n_edges;
+    int32_t cut_min;
+    int32_t cut_range;
+    int32_t n_groups;
+    int32_t cut_shift;   // cut_min - plan.cut_min: offset into a phase table row
+    int64_t tt_off[4];   // byte offset of the C_tt table of each group
+    int32_t tt_min[4];   // value subtracted before storing C_tt as a byte
+};
+
+struct PassArgs {
+    const ConeHbm* cones;      // cones of this k-class
+    const int32_t* e_a;        // flattened cone edges (qubit pairs) and weights
+    const int32_t* e_b;
+    const int32_t* e_w;
+    const uint8_t* tt;         // C_tt tables
+    float2* phi;               // state buffer [batch][2^k]
+    float2* lam;               // adjoint buffer [batch][2^k]
+    double* gpart;             // per (item, tile) partial sums [batch][tiles][2p + 1]
+    int64_t item0;             // first item of the batch (item = slot * P + point)
+    int32_t n_batch;           // items in the batch
+    int32_t k;                 // cone qubits (same for every cone of the class)
+    int32_t group;             // pass group
+    int32_t la, lb;            // layers (1-based) of mixer A / phase + mixer B
+    int32_t m0a, m0b;          // qubits of layers la / lb undone by earlier reverse passes
+    int32_t rowcap;            // phase row capacity (largest cut range)
+    int32_t fix_layer;         // > 0: the loaded psi is rescaled by |kappa_fix_layer|^fix_pow
+    int32_t fix_pow;
+    EvalArgs ea;
+};
+
+template <bool GR>
+struct Hz {
+    static constexpr int AB = GR ? 4 : 5;
+    static constexpr int A = 1 << AB;
+    static constexpr int W = 1 << (HT - AB);        // threads per tile
+    static constexpr uint32_t NPAD = HN + (HN >> 5) + (HN >> 10);
+    static constexpr int ROT_IO0 = HT - AB;          // I/O layout of group 0: lanes on tile bits 0..5
+    static constexpr int ROT_IOJ = 9 - AB;           // I/O layout of groups >= 1: lanes on tile bits 9..12, 0, 1
+};
+
+__device__ constexpr uint32_t rotl13(uint32_t x, int s) {
+    s %= HT;
+    return s == 0 ? x : (((x << s) | (x >> (HT - s))) & (HN - 1u));
+}
+template <bool GR, int ROT>
+__device__ constexpr uint32_t hroff(int r) { return rotl13(static_cast<uint32_t>(r), ROT); }
+template <bool GR, int ROT>
+__device__ __forceinline__ uint32_t htbase(uint32_t tau) { return rotl13(tau << Hz<GR>::AB, ROT); }
+
+template <bool GR, int RF, int RT, int A>
+__device__ __forceinline__ void hxpose(float2 (&v)[A], float2* xb, uint32_t tau) {
+    float2* pf = xb + opaque_u32(pad(htbase<GR, RF>(tau)));
+    const float2* pt = xb + opaque_u32(pad(htbase<GR, RT>(tau)));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) pf[pad(hroff<GR, RF>(r))] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) v[r] = pt[pad(hroff<GR, RT>(r))];
+}
+
+// Mixer on the processed tile bits of layout ROT (tile bit b is processed when bit b of
+// pm is set; a butterfly with tau = 0 is the identity).  Wrapped bits belong to rotation 0.
+template <bool GR, int ROT, int A>
+__device__ __forceinline__ void hmix(float2 (&v)[A], float t, uint32_t pm) {
+    constexpr int AB = Hz<GR>::AB;
+#pragma unroll
+    for (int i = 0; i < AB; ++i) {
+        if (ROT + i >= HT) continue;
+        const float ti = ((pm >> (ROT + i)) & 1u) ? t : 0.f;
+        int nb = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                bfly(v[r], v[r | (1 << i)], ti);
+                if ((++nb & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Undo the mixer on the processed bits of layout ROT for psi and lambda; returns the
+// weighted share of Im <lambda| sum_j X_j |psi> (see unmix_stage2).
+template <bool GR, int ROT, int A>
+__device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w, uint32_t pm) {
+    constexpr int AB = Hz<GR>::AB;
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < AB; ++i) {
+        if (ROT + i >= HT) continue;
+        const bool act = (pm >> (ROT + i)) & 1u;
+        const float ti = act ? -t : 0.f;
+        float a0 = 0.f, a1 = 0.f;
+        int np = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                const int r2 = r | (1 << i);
+                bfly(f[r], f[r2], ti);
+                bfly(l[r], l[r2], ti);
+                if (np++ & 1) xacc(a1, l[r], l[r2], f[r], f[r2]);
+                else xacc(a0, l[r], l[r2], f[r], f[r2]);
+                if ((np & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        const float wn = act ? w * k2 : w;
+        acc = fmaf(act ? wn : 0.f, a0 + a1, acc);
+        w = wn;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// Processing layouts: rotations 0, AB, 2 AB, ...  Group 0 needs all 13 tile bits,
+// groups >= 1 at most 9 (tile bits 0..8).
+template <bool GR, bool G0>
+struct HStages {
+    static constexpr int AB = Hz<GR>::AB;
+    static constexpr int NB = G0 ? HT : 9;
+    static constexpr int S = (NB + AB - 1) / AB;
+    static constexpr int rot(int s) { return s * AB; }
+    static constexpr int IO = G0 ? Hz<GR>::ROT_IO0 : Hz<GR>::ROT_IOJ;
+};
+
+// Forward mixer over the group, visiting layouts S-1 .. 0 (DESC) or 0 .. S-1, starting in
+// layout FROM_ROT.  Ends in the last visited layout.
+template <bool GR, bool G0, bool DESC, int FROM_ROT, int A>
+__device__ __forceinline__ void hmix_group(float2 (&f)[A], float2* xb, uint32_t tau, float t, uint32_t pm) {
+    using H = HStages<GR, G0>;
+    static_for<0, H::S>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr int st = DESC ? H::S - 1 - j : j;
+        constexpr int prev = (j == 0) ? FROM_ROT : H::rot(DESC ? H::S - j : j - 1);
+        if constexpr (prev != H::rot(st)) hxpose<GR, prev, H::rot(st)>(f, xb, tau);
+        hmix<GR, H::rot(st)>(f, t, pm);
+    });
+}
+
+template <bool GR, bool G0, bool DESC, int FROM_ROT, int A>
+__device__ __forceinline__ float hunmix_group(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t,
+                                              float k2, float& w, uint32_t pm) {
+    using H = HStages<GR, G0>;
+    float acc = 0.f;
+    static_for<0, H::S>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr int st = DESC ? H::S - 1 - j : j;
+        constexpr int prev = (j == 0) ? FROM_ROT : H::rot(DESC ? H::S - j : j - 1);
+        if constexpr (prev != H::rot(st)) {
+            hxpose<GR, prev, H::rot(st)>(f, xb, tau);
+            hxpose<GR, prev, H::rot(st)>(l, xb, tau);
+        }
+        acc += hunmix2<GR, H::rot(st)>(f, l, t, k2, w, pm);
+    });
+    return acc;
+}
+
+// Geometry of pass group grp for a k-qubit cone: tile bit i -> global bit gmap(i).
+__device__ __forceinline__ int hgroup_bits(int k, int grp, int i, int& h) {
+    if (grp == 0) {
+        h = HT;
+        return i;
+    }
+    const int lo = HT + 9 * (grp - 1);
+    h = min(k, lo + 9) - lo;
+    if (i < h) return lo + i;
+    if (i < 9) return 4 + (i - h);
+    return i - 9;
+}
+
+// Block-wide sum in a fixed order (identical in every thread).
+template <int W>
+__device__ __forceinline__ double block_sum(double x, double* red) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = x;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W / 64; ++w) s += red[w];
+    return s;
+}
+
+template <int KIND, bool G0>
+__global__ void __launch_bounds__((Hz<(KIND >= GR_GEN_FINAL)>::W))
+k_pass(PassArgs pa) {
+    constexpr bool GR = KIND >= GR_GEN_FINAL;
+    using H = Hz<GR>;
+    using HS = HStages<GR, G0>;
+    constexpr int A = H::A;
+    constexpr int NW = (A + 3) / 4;
+    constexpr bool GEN = (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL);
+    constexpr bool FINAL = (KIND == FWD_GEN_FINAL || KIND == FWD_BND_FINAL || KIND == GR_GEN_FINAL ||
+                            KIND == GR_BND_FINAL);
+    __shared__ float2 xbuf[H::NPAD];
+    __shared__ __attribute__((aligned(16))) uint8_t ttl[HN];
+    __shared__ uint32_t gstr[HT];
+    __shared__ int32_t lcoef[HT];
+    __shared__ double red[H::W / 64];
+    __shared__ int32_t k0_sh;
+    extern __shared__ float2 rows[];   // [p][rowcap]
+
+    const int tid = threadIdx.x;
+    const uint32_t tau = static_cast<uint32_t>(tid);
+    const int k = pa.k;
+    const int64_t tiles = int64_t{1} << (k - HT);
+    const int64_t bslot = blockIdx.x / tiles;             // item within the batch
+    const int64_t tile = blockIdx.x - bslot * tiles;
+    const int64_t item = pa.item0 + bslot;
+    const int P = pa.ea.P, p = pa.ea.p;
+    const int64_t cslot = item / P;
+    const int point = static_cast<int>(item - cslot * P);
+    const ConeHbm cd = pa.cones[cslot];
+
+    // ---- group geometry, outer bits, and the linear cut coefficients of this tile
+    int h = 0;
+    uint32_t tmask = 0;  // global bits inside the tile
+    for (int i = 0; i < HT; ++i) tmask |= 1u << hgroup_bits(k, pa.group, i, h);
+    uint64_t xo = 0;     // global index bits of the tile's outer part
+    {
+        int64_t o = tile;
+        for (int b = 0; b < k; ++b)
+            if (!((tmask >> b) & 1u)) {
+                xo |= static_cast<uint64_t>(o & 1) << b;
+                o >>= 1;
+            }
+    }
+    const uint32_t pm = (pa.group == 0) ? (HN - 1u) : ((1u << h) - 1u);
+    if (tid < HT) {
+        int hh;
+        const int gb = hgroup_bits(k, pa.group, tid, hh);
+        gstr[tid] = 1u << gb;
+        // WO_b - 2 W1_b for tile bit tid
+        int32_t wo = 0, w1 = 0;
+        for (int e = 0; e < cd.n_edges; ++e) {
+            const int a = pa.e_a[cd.edge_off + e], b = pa.e_b[cd.edge_off + e], w = pa.e_w[cd.edge_off + e];
+            const int other = (a == gb) ? b : ((b == gb) ? a : -1);
+            if (other >= 0 && !((tmask >> other) & 1u)) {
+                wo += w;
+                if ((xo >> other) & 1u) w1 += w;
+            }
+        }
+        lcoef[tid] = wo - 2 * w1;
+    }
+    if (tid == 0) {   // C_oo(o) + sum_b W1_b
+        int32_t c = 0;
+        for (int e = 0; e < cd.n_edges; ++e) {
+            const int a = pa.e_a[cd.edge_off + e], b = pa.e_b[cd.edge_off + e], w = pa.e_w[cd.edge_off + e];
+            const bool ia = (tmask >> a) & 1u, ib = (tmask >> b) & 1u;
+            const int xa = static_cast<int>((xo >> a) & 1u), xb2 = static_cast<int>((xo >> b) & 1u);
+            if (!ia && !ib) c += w * (xa ^ xb2);
+            else if (ia && !ib) c += w * xb2;
+            else if (!ia && ib) c += w * xa;
+        }
+        k0_sh = c + pa.cones[cslot].tt_min[pa.group] - cd.cut_min;
+    }
+    {   // C_tt table and the phase rows of this item
+        const uint8_t* src = pa.tt + pa.cones[cslot].tt_off[pa.group];
+        for (uint32_t q = tau * 16; q < HN; q += H::W * 16)
+            *reinterpret_cast<uint4*>(ttl + q) = *reinterpret_cast<const uint4*>(src + q);
+        const float2* ph0 = pa.ea.phase + static_cast<size_t>(point) * p * pa.ea.R + cd.cut_shift;
+        for (int l = 0; l < p; ++l)
+            for (int c = tid; c < cd.cut_range; c += H::W)
+                rows[l * pa.rowcap + c] = ph0[static_cast<size_t>(l) * pa.ea.R + c];
+    }
+    __syncthreads();
+    float2* xb = xbuf;
+    const float2* mix0 = pa.ea.mix + static_cast<size_t>(point) * p;
+    auto kpowK = [&](float k2) { return exp2f(0.5f * k * log2f(k2)); };
+    const float k2p = mix0[p - 1].y;
+
+    // packed cut values (minus cut_min) of the thread's amplitudes in layout rotation 0
+    uint32_t pk0[NW];
+    {
+        const uint32_t qb = htbase<GR, 0>(tau);
+        int32_t lthr = k0_sh;
+#pragma unroll
+        for (int i = 0; i < HT; ++i)
+            if ((qb >> i) & 1u) lthr += lcoef[i];
+#pragma unroll
+        for (int w2 = 0; w2 < NW; ++w2) pk0[w2] = 0u;
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            int32_t c = lthr + ttl[qb | hroff<GR, 0>(r)];
+#pragma unroll
+            for (int i = 0; i < H::AB; ++i)
+                if ((r >> i) & 1) c += lcoef[i];
+            pk0[r >> 2] |= static_cast<uint32_t>(c) << (8 * (r & 3));
+        }
+    }
+
+    // ---- global addressing of the I/O layout
+    constexpr int RIO = HS::IO;
+    const uint32_t qio = htbase<GR, RIO>(tau);
+    uint64_t gbase = xo;
+#pragma unroll
+    for (int i = 0; i < HT; ++i)
+        if ((qio >> i) & 1u) gbase += gstr[i];
+    const size_t item_off = static_cast<size_t>(bslot) << k;
+    auto io_off = [&](int r) -> uint64_t {
+        uint64_t o = 0;
+        const uint32_t q = hroff<GR, RIO>(r);
+#pragma unroll
+        for (int i = 0; i < HT; ++i)
+            if ((q >> i) & 1u) o += gstr[i];
+        return o;
+    };
+    auto load = [&](float2 (&v)[A], const float2* buf) {
+        const float2* b = buf + item_off + gbase;
+#pragma unroll
+        for (int r = 0; r < A; ++r) v[r] = b[io_off(r)];
+    };
+    auto store = [&](const float2 (&v)[A], float2* buf) {
+        float2* b = buf + item_off + gbase;
+#pragma unroll
+        for (int r = 0; r < A; ++r) b[io_off(r)] = v[r];
+    };
+    double* gp = pa.gpart + (static_cast<size_t>(bslot) * tiles + tile) * (2 * p + 1);
+
+    float2 f[A];
+    constexpr int RL = HS::rot(HS::S - 1);   // last processing layout
+    // ---------------------------------------------------------------- forward part
+    if constexpr (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL) {
+        gen_stage(f, pk0, rows, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
+        if constexpr (KIND == FWD_GEN_MIX) {
+            hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[0].x, pm);
+            hxpose<GR, RL, RIO>(f, xb, tau);
+            store(f, pa.phi);
+            return;
+        }
+    }
+    if constexpr (KIND == FWD_MIX || KIND == FWD_BND_MIX || KIND == FWD_BND_FINAL || KIND == GR_BND_FINAL) {
+        load(f, pa.phi);
+        const float2 tka = mix0[pa.la - 1];
+        hmix_group<GR, G0, true, RIO>(f, xb, tau, tka.x, pm);     // ends in rotation 0
+        if constexpr (KIND == FWD_MIX) {
+            hxpose<GR, 0, RIO>(f, xb, tau);
+            store(f, pa.phi);
+            return;
+        }
+        phase_stage(f, pk0, rows + (pa.lb - 1) * pa.rowcap, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
+        if constexpr (KIND == FWD_BND_MIX) {
+            hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[pa.lb - 1].x, pm);
+            hxpose<GR, RL, RIO>(f, xb, tau);
+            store(f, pa.phi);
+            return;
+        }
+    }
+    // ---------------------------------------------------------------- final layer
+    if constexpr (FINAL) {
+        const float tp = mix0[p - 1].x;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & 1)) bfly(f[r], f[r | 1], tp);
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & 2)) bfly(f[r], f[r | 2], tp);
+        double zzp = 0.0;
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const double pr = static_cast<double>(fmaf(f[r].x, f[r].x, f[r].y * f[r].y));
+            zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
+        }
+        const double zz = block_sum<H::W>(zzp, red);
+        if (tid == 0) gp[0] = zz;
+        if constexpr (GR) {
+            float2 lm[A];
+#pragma unroll
+            for (int r = 0; r < A; ++r) lm[r] = (((r ^ (r >> 1)) & 1) ? make_float2(-f[r].x, -f[r].y) : f[r]);
+            float acc = 0.f;
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 1)) xacc(acc, lm[r], lm[r | 1], f[r], f[r | 1]);
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 2)) xacc(acc, lm[r], lm[r | 2], f[r], f[r | 2]);
+            const double gbp = block_sum<H::W>(2.0 * static_cast<double>(acc), red);
+            if (tid == 0) gp[1 + p + p - 1] = gbp;
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 2)) { bfly(f[r], f[r | 2], -tp); bfly(lm[r], lm[r | 2], -tp); }
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 1)) { bfly(f[r], f[r | 1], -tp); bfly(lm[r], lm[r | 1], -tp); }
+            const float mu = k2p;
+            if constexpr (KIND == GR_GEN_FINAL) {
+                const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
+                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
+                if (tid == 0) gp[1] = gc;
+            } else {
+                const float a = cgrad_stage<true>(f, lm, pk0, rows + (p - 1) * pa.rowcap, cd.cut_min, mu);
+                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
+                if (tid == 0) gp[1 + p - 1] = gc;
+                // undo mixer la = p-1 on this group (state sits in rotation 0)
+                const float2 tka = mix0[pa.la - 1];
+                float w = exp2f(pa.m0a * log2f(tka.y));
+                const float b = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, w, pm);
+                const double gb = block_sum<H::W>(2.0 * static_cast<double>(b), red);
+                if (tid == 0) gp[1 + p + pa.la - 1] += gb;
+                hxpose<GR, RL, RIO>(lm, xb, tau);
+                store(lm, pa.lam);
+            }
+        }
+    }
+    // ---------------------------------------------------------------- reverse passes
+    if constexpr (KIND == RV_GEN_MIX || KIND == RV_MIX || KIND == RV_BND_MIX) {
+        float2 lm[A];
+        load(f, pa.phi);
+        load(lm, pa.lam);
+        if (pa.fix_layer > 0) {
+            // The first reverse pass reads psi as the forward sweep left it: the final pass
+            // mixed layer p-1 on group 0 (13 qubits) forward but lambda has undone them, and
+            // the factored mixer scales by 1/|kappa| per qubit in both directions, so psi
+            // carries |kappa|^(k-13) where lambda carries |kappa|^13.
+            const float sc = exp2f(0.5f * pa.fix_pow * log2f(mix0[pa.fix_layer - 1].y));
+#pragma unroll
+            for (int r = 0; r < A; ++r) f[r] = make_float2(sc * f[r].x, sc * f[r].y);
+        }
+        if constexpr (KIND == RV_MIX) {
+            const float2 tka = mix0[pa.la - 1];
+            float w = exp2f(pa.m0a * log2f(tka.y));
+            const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tka.x, tka.y, w, pm);
+            const double gb = block_sum<H::W>(2.0 * static_cast<double>(b), red);
+            if (tid == 0) gp[1 + p + pa.la - 1] += gb;
+            hxpose<GR, 0, RIO>(f, xb, tau);
+            hxpose<GR, 0, RIO>(lm, xb, tau);
+            store(f, pa.phi);
+            store(lm, pa.lam);
+        } else {
+            // undo mixer lb (the first group of layer lb in forward order: after it, layer lb
+            // is completely undone), then gamma_lb
+            const float2 tkb = mix0[pa.lb - 1];
+            float w = exp2f(pa.m0b * log2f(tkb.y));
+            const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tkb.x, tkb.y, w, pm);
+            const double gb = block_sum<H::W>(2.0 * static_cast<double>(b), red);
+            if (tid == 0) gp[1 + p + pa.lb - 1] += gb;
+            const float mu = (pa.lb == p) ? k2p : kpowK(tkb.y);
+            if constexpr (KIND == RV_GEN_MIX) {
+                const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
+                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
+                if (tid == 0) gp[1] += gc;
+            } else {
+                const float a = cgrad_stage<true>(f, lm, pk0, rows + (pa.lb - 1) * pa.rowcap, cd.cut_min, mu);
+                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
+                if (tid == 0) gp[1 + pa.lb - 1] += gc;
+                const float2 tka = mix0[pa.la - 1];
+                float wa = exp2f(pa.m0a * log2f(tka.y));
+                const float ba = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, wa, pm);
+                const double gba = block_sum<H::W>(2.0 * static_cast<double>(ba), red);
+                if (tid == 0) gp[1 + p + pa.la - 1] += gba;
+                hxpose<GR, RL, RIO>(f, xb, tau);
+                hxpose<GR, RL, RIO>(lm, xb, tau);
+                store(f, pa.phi);
+                store(lm, pa.lam);
+            }
+        }
+    }
+}
+
+}  // namespace qaoa

@@ -3,6 +3,7 @@
 #include "runtime.hpp"
 
 #include <algorithm>
+#include <cstring>
 #include <numeric>
 
 namespace qaoa {
@@ -36,6 +37,86 @@ qaoa_status grow(T*& ptr, size_t& cap, size_t need, std::string& msg) {
     return QAOA_OK;
 }
 
+// Pass groups of a k-qubit HBM cone: group 0 = qubits 0..12, group j >= 1 = nine of the
+// remaining qubits; tile bit i of group g maps to global bit hbm_group_global_bit(k, g, i)
+// (the same map as hgroup_bits in hbm_impl.hpp).
+int hbm_group_global_bit(int k, int grp, int i) {
+    if (grp == 0) return i;
+    const int lo = 13 + 9 * (grp - 1);
+    const int h = std::min(k, lo + 9) - lo;
+    if (i < h) return lo + i;
+    if (i < 9) return 4 + (i - h);
+    return i - 9;
+}
+
+}  // namespace
+
+int hbm_groups_of(int k) { return 1 + (k - 13 + 8) / 9; }
+
+int hbm_group_qubits(int k, int grp) {
+    if (grp == 0) return 13;
+    const int lo = 13 + 9 * (grp - 1);
+    return std::min(k, lo + 9) - lo;
+}
+
+// Forward program: layer l (1 <= l <= p-1) visits the groups in descending order when
+// p-1-l is even, ascending otherwise, so layer p-1 ends on group 0 and consecutive layers
+// share a pass.  With grad, the last pass is the fused final/adjoint pass and the earlier
+// passes follow in reverse as RV_* passes; m0a / m0b count the qubits of a layer already
+// undone by earlier reverse passes.
+std::vector<PassSpec> hbm_program(int k, int p, bool grad) {
+    std::vector<PassSpec> fwd;
+    const int n = hbm_groups_of(k);
+    if (p == 1) {
+        fwd.push_back({grad ? GR_GEN_FINAL : FWD_GEN_FINAL, 0, 0, 1, 0, 0, 0, 0});
+        return fwd;
+    }
+    auto group_at = [&](int l, int j) { return (((p - 1 - l) & 1) == 0) ? n - 1 - j : j; };
+    fwd.push_back({FWD_GEN_MIX, group_at(1, 0), 0, 1, 0, 0, 0, 0});
+    for (int l = 1; l <= p - 1; ++l)
+        for (int j = 1; j < n; ++j) {
+            const int g = group_at(l, j);
+            if (j < n - 1) fwd.push_back({FWD_MIX, g, l, 0, 0, 0, 0, 0});
+            else if (l + 1 <= p - 1) fwd.push_back({FWD_BND_MIX, g, l, l + 1, 0, 0, 0, 0});
+            else fwd.push_back({FWD_BND_FINAL, g, l, p, 0, 0, 0, 0});
+        }
+    if (!grad) return fwd;
+    std::vector<PassSpec> out(fwd.begin(), fwd.end() - 1);
+    std::vector<int> undone(p + 2, 0);
+    PassSpec fin = fwd.back();
+    fin.kind = GR_BND_FINAL;
+    fin.m0a = undone[fin.la];
+    undone[fin.la] += hbm_group_qubits(k, fin.group);
+    out.push_back(fin);
+    for (int i = static_cast<int>(fwd.size()) - 2; i >= 0; --i) {
+        PassSpec r = fwd[i];
+        const int h = hbm_group_qubits(k, r.group);
+        if (r.kind == FWD_GEN_MIX) {
+            r.kind = RV_GEN_MIX;
+            r.m0b = undone[r.lb];
+            undone[r.lb] += h;
+        } else if (r.kind == FWD_MIX) {
+            r.kind = RV_MIX;
+            r.m0a = undone[r.la];
+            undone[r.la] += h;
+        } else {
+            r.kind = RV_BND_MIX;
+            r.m0b = undone[r.lb];
+            undone[r.lb] += h;
+            r.m0a = undone[r.la];
+            undone[r.la] += h;
+        }
+        if (i == static_cast<int>(fwd.size()) - 2) {
+            r.fix_layer = fin.la;
+            r.fix_pow = k - 2 * hbm_group_qubits(k, 0);
+        }
+        out.push_back(r);
+    }
+    return out;
+}
+
+namespace {
+
 qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
@@ -51,16 +132,14 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         return QAOA_OK;
     }
     const HostPlan& hp = P->hp;
-    const int64_t M = static_cast<int64_t>(hp.cones.size());
-    for (const auto& c : hp.cones)
-        if (c.k > P->opt.k_lds_max) {
-            msg = "cones above " + std::to_string(P->opt.k_lds_max) + " qubits are not supported by this build";
-            return QAOA_ECONE;
-        }
-    // workgroup-resident cones, grouped by K
-    std::vector<int64_t> ord(M);
-    std::iota(ord.begin(), ord.end(), 0);
+    const int64_t Mall = static_cast<int64_t>(hp.cones.size());
+    // workgroup-resident cones (k <= k_lds_max), grouped by K; larger cones go to the
+    // HBM-resident passes, grouped by k
+    std::vector<int64_t> ord, hord;
+    for (int64_t m = 0; m < Mall; ++m) (hp.cones[m].k <= P->opt.k_lds_max ? ord : hord).push_back(m);
     std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return hp.cones[a].k < hp.cones[b].k; });
+    std::stable_sort(hord.begin(), hord.end(), [&](int64_t a, int64_t b) { return hp.cones[a].k < hp.cones[b].k; });
+    const int64_t M = static_cast<int64_t>(ord.size());
     std::vector<ConeDev> cd(M);
     std::vector<int32_t> ea, eb, ew;
     int64_t cut_bytes = 0;
@@ -85,29 +164,66 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         P->lds_groups.back().count += 1;
         P->lds_groups.back().rowcap = std::max(P->lds_groups.back().rowcap, d.cut_range);
     }
-    int32_t *d_ea = nullptr, *d_eb = nullptr, *d_ew = nullptr;
+    // HBM-class descriptors; their edges follow the workgroup-resident ones
+    std::vector<ConeHbm> hc(hord.size());
+    int64_t tt_bytes = 0;
+    int max_groups = 1;
+    P->hbm_groups.clear();
+    for (size_t s = 0; s < hord.size(); ++s) {
+        const Cone& c = hp.cones[hord[s]];
+        ConeHbm& d = hc[s];
+        std::memset(&d, 0, sizeof(d));
+        d.orbit = static_cast<int32_t>(hord[s]);
+        d.k = c.k;
+        d.edge_off = static_cast<int32_t>(ea.size());
+        d.n_edges = static_cast<int32_t>(c.ea.size());
+        d.cut_min = c.cut_min;
+        d.cut_range = c.cut_max - c.cut_min + 1;
+        d.cut_shift = c.cut_min - hp.cut_min;
+        d.n_groups = hbm_groups_of(c.k);
+        max_groups = std::max(max_groups, d.n_groups);
+        for (int g = 0; g < d.n_groups; ++g) {
+            // tile bits of group g; C_tt ranges over the edges with both ends inside
+            std::vector<char> in(32, 0);
+            for (int i = 0; i < 13; ++i) in[hbm_group_global_bit(c.k, g, i)] = 1;
+            int32_t tmin = 0, tmax = 0;
+            for (size_t e = 0; e < c.ea.size(); ++e)
+                if (in[c.ea[e]] && in[c.eb[e]]) (c.ew[e] < 0 ? tmin : tmax) += c.ew[e];
+            d.tt_min[g] = tmin;
+            d.tt_off[g] = tt_bytes;
+            tt_bytes += 8192;
+        }
+        ea.insert(ea.end(), c.ea.begin(), c.ea.end());
+        eb.insert(eb.end(), c.eb.begin(), c.eb.end());
+        ew.insert(ew.end(), c.ew.begin(), c.ew.end());
+        if (P->hbm_groups.empty() || P->hbm_groups.back().K != c.k)
+            P->hbm_groups.push_back({c.k, static_cast<int64_t>(s), 0, 1});
+        P->hbm_groups.back().count += 1;
+        P->hbm_groups.back().rowcap = std::max(P->hbm_groups.back().rowcap, d.cut_range);
+    }
     const size_t ne = std::max<size_t>(ea.size(), 1);
     QCHECK(hipMalloc(&P->d_cones, std::max<size_t>(cd.size(), 1) * sizeof(ConeDev)));
     QCHECK(hipMalloc(&P->d_cut, std::max<int64_t>(cut_bytes, 16)));
     QCHECK(hipMalloc(&P->d_W, std::max<size_t>(hp.W.size(), 1) * sizeof(double)));
-    QCHECK(hipMalloc(&d_ea, ne * sizeof(int32_t)));
-    QCHECK(hipMalloc(&d_eb, ne * sizeof(int32_t)));
-    QCHECK(hipMalloc(&d_ew, ne * sizeof(int32_t)));
-    if (M) {
-        QCHECK(hipMemcpy(P->d_cones, cd.data(), cd.size() * sizeof(ConeDev), hipMemcpyHostToDevice));
-        QCHECK(hipMemcpy(P->d_W, hp.W.data(), hp.W.size() * sizeof(double), hipMemcpyHostToDevice));
-    }
+    QCHECK(hipMalloc(&P->d_ea, ne * sizeof(int32_t)));
+    QCHECK(hipMalloc(&P->d_eb, ne * sizeof(int32_t)));
+    QCHECK(hipMalloc(&P->d_ew, ne * sizeof(int32_t)));
+    QCHECK(hipMalloc(&P->d_hcones, std::max<size_t>(hc.size(), 1) * sizeof(ConeHbm)));
+    QCHECK(hipMalloc(&P->d_tt, std::max<int64_t>(tt_bytes, 16)));
+    if (M) QCHECK(hipMemcpy(P->d_cones, cd.data(), cd.size() * sizeof(ConeDev), hipMemcpyHostToDevice));
+    if (Mall) QCHECK(hipMemcpy(P->d_W, hp.W.data(), hp.W.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (!hc.empty()) QCHECK(hipMemcpy(P->d_hcones, hc.data(), hc.size() * sizeof(ConeHbm), hipMemcpyHostToDevice));
     if (!ea.empty()) {
-        QCHECK(hipMemcpy(d_ea, ea.data(), ea.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        QCHECK(hipMemcpy(d_eb, eb.data(), eb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        QCHECK(hipMemcpy(d_ew, ew.data(), ew.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        QCHECK(hipMemcpy(P->d_ea, ea.data(), ea.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        QCHECK(hipMemcpy(P->d_eb, eb.data(), eb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        QCHECK(hipMemcpy(P->d_ew, ew.data(), ew.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    QCHECK(launch_cut_tables(P->d_cones, M, d_ea, d_eb, d_ew, P->d_cut, nullptr));
+    QCHECK(launch_cut_tables(P->d_cones, M, P->d_ea, P->d_eb, P->d_ew, P->d_cut, nullptr));
+    QCHECK(launch_tt_tables(P->d_hcones, static_cast<int64_t>(hc.size()), max_groups, P->d_ea, P->d_eb, P->d_ew,
+                            P->d_tt, nullptr));
     QCHECK(hipDeviceSynchronize());
-    hipFree(d_ea);
-    hipFree(d_eb);
-    hipFree(d_ew);
-    P->resident_bytes = cd.size() * sizeof(ConeDev) + static_cast<size_t>(cut_bytes) + hp.W.size() * sizeof(double);
+    P->resident_bytes = cd.size() * sizeof(ConeDev) + static_cast<size_t>(cut_bytes) + hp.W.size() * sizeof(double) +
+                        hc.size() * sizeof(ConeHbm) + static_cast<size_t>(tt_bytes) + 3 * ne * sizeof(int32_t);
     P->device = dev;
     P->dev_ready = true;
     return QAOA_OK;
@@ -199,6 +315,68 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
         }
         QCHECK(tm.end());
     }
+    // ---- HBM-resident cones: batches of items through the pass program
+    for (const auto& grp : P->hbm_groups) {
+        const int k = grp.K;
+        const int64_t items = grp.count * n_points;
+        const int64_t tiles = int64_t{1} << (k - HT);
+        const int nvals = grad ? 2 * p + 1 : 1;     // values reduced per item
+        const int stride = 2 * p + 1;                // values stored per (item, tile)
+        const bool need_phi = p >= 2;
+        const bool need_lam = grad && p >= 2;
+        const size_t state_bytes = (size_t{1} << k) * sizeof(float2);
+        const size_t per_item = (need_phi ? state_bytes : 0) + (need_lam ? state_bytes : 0) +
+                                static_cast<size_t>(tiles) * stride * sizeof(double);
+        size_t budget = static_cast<size_t>(P->opt.mem_budget_bytes);
+        if (budget == 0) {
+            size_t fr = 0, tot = 0;
+            QCHECK(hipMemGetInfo(&fr, &tot));
+            const size_t held = P->cap_phi * sizeof(float2) + P->cap_lam * sizeof(float2) + P->cap_gpart * sizeof(double);
+            budget = static_cast<size_t>(0.85 * static_cast<double>(fr + held));
+        }
+        int64_t B = static_cast<int64_t>(budget / per_item);
+        if (B < 1) {
+            msg = "one " + std::to_string(k) + "-qubit item needs " + std::to_string(per_item) +
+                  " bytes, more than the memory budget of " + std::to_string(budget);
+            return QAOA_ENOMEM;
+        }
+        B = std::min<int64_t>(B, items);
+        if (need_phi && (st = grow(P->d_phi, P->cap_phi, static_cast<size_t>(B) << k, msg)) != QAOA_OK) return st;
+        if (need_lam && (st = grow(P->d_lam, P->cap_lam, static_cast<size_t>(B) << k, msg)) != QAOA_OK) return st;
+        if ((st = grow(P->d_gpart, P->cap_gpart, static_cast<size_t>(B) * tiles * stride, msg)) != QAOA_OK) return st;
+        const std::vector<PassSpec> prog = hbm_program(k, p, grad);
+        QCHECK(tm.begin(k, items));
+        for (int64_t i0 = 0; i0 < items; i0 += B) {
+            const int64_t nb = std::min<int64_t>(B, items - i0);
+            QCHECK(launch_fill_zero(P->d_gpart, nb * tiles * stride, stream));
+            for (const PassSpec& ps : prog) {
+                PassArgs pa{};
+                pa.cones = P->d_hcones + grp.first;
+                pa.e_a = P->d_ea;
+                pa.e_b = P->d_eb;
+                pa.e_w = P->d_ew;
+                pa.tt = P->d_tt;
+                pa.phi = P->d_phi;
+                pa.lam = P->d_lam;
+                pa.gpart = P->d_gpart;
+                pa.item0 = i0;
+                pa.n_batch = static_cast<int32_t>(nb);
+                pa.k = k;
+                pa.group = ps.group;
+                pa.la = ps.la;
+                pa.lb = ps.lb;
+                pa.m0a = ps.m0a;
+                pa.m0b = ps.m0b;
+                pa.rowcap = grp.rowcap;
+                pa.fix_layer = ps.fix_layer;
+                pa.fix_pow = ps.fix_pow;
+                pa.ea = ea;
+                QCHECK(launch_pass(ps.kind, pa, stream));
+            }
+            QCHECK(launch_tile_reduce(P->d_hcones + grp.first, P->d_gpart, i0, nb, tiles, stride, nvals, ea, stream));
+        }
+        QCHECK(tm.end());
+    }
     QCHECK(tm.begin(-2, n_points));
     QCHECK(launch_combine(P->d_W, zz, g, M, p, n_points, energy, dgamma, dbeta, stream));
     QCHECK(tm.end());
@@ -220,6 +398,20 @@ void release_device(qaoa_plan_s* P) {
     hipFree(P->d_mix);
     hipFree(P->d_zz);
     hipFree(P->d_g);
+    hipFree(P->d_hcones);
+    hipFree(P->d_ea);
+    hipFree(P->d_eb);
+    hipFree(P->d_ew);
+    hipFree(P->d_tt);
+    hipFree(P->d_phi);
+    hipFree(P->d_lam);
+    hipFree(P->d_gpart);
+    P->d_hcones = nullptr;
+    P->d_ea = P->d_eb = P->d_ew = nullptr;
+    P->d_tt = nullptr;
+    P->d_phi = P->d_lam = nullptr;
+    P->d_gpart = nullptr;
+    P->cap_phi = P->cap_lam = P->cap_gpart = 0;
     P->d_cones = nullptr;
     P->d_cut = nullptr;
     P->d_W = nullptr;

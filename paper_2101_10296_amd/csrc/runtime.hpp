@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "device.hpp"
+#include "hbm_impl.hpp"
 #include "plan.hpp"
 #include "qaoa.h"
 
@@ -26,6 +27,17 @@ struct qaoa_plan_s {
     std::vector<Group> lds_groups;      // workgroup-resident cones, grouped by K
     qaoa::ConeDev* d_cones = nullptr;
     uint8_t* d_cut = nullptr;
+    // HBM-resident cones, grouped by k
+    struct HGroup {
+        int K;
+        int64_t first;
+        int64_t count;
+        int32_t rowcap;
+    };
+    std::vector<HGroup> hbm_groups;
+    qaoa::ConeHbm* d_hcones = nullptr;
+    int32_t *d_ea = nullptr, *d_eb = nullptr, *d_ew = nullptr;
+    uint8_t* d_tt = nullptr;
     double* d_W = nullptr;
     size_t resident_bytes = 0;
 
@@ -44,6 +56,10 @@ struct qaoa_plan_s {
     float2* d_mix = nullptr;
     double* d_zz = nullptr;
     double* d_g = nullptr;
+    size_t cap_phi = 0, cap_lam = 0, cap_gpart = 0;
+    float2* d_phi = nullptr;
+    float2* d_lam = nullptr;
+    double* d_gpart = nullptr;
 };
 
 namespace qaoa {
@@ -63,6 +79,22 @@ hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, 
                          float2* phase, float2* mix, hipStream_t st);
 hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
                              const int32_t* ew, uint8_t* tables, hipStream_t st);
+hipError_t launch_pass(int kind, const PassArgs& pa, hipStream_t st);
+hipError_t launch_tt_tables(const ConeHbm* cones, int64_t n_cones, int max_groups, const int32_t* ea,
+                            const int32_t* eb, const int32_t* ew, uint8_t* tt, hipStream_t st);
+hipError_t launch_fill_zero(double* x, int64_t n, hipStream_t st);
+hipError_t launch_tile_reduce(const ConeHbm* cones, const double* gpart, int64_t item0, int64_t n_batch,
+                              int64_t tiles, int32_t stride, int32_t nvals, const EvalArgs& ea, hipStream_t st);
+
+// One pass of the HBM program (see hbm_impl.hpp).
+struct PassSpec {
+    int kind, group, la, lb, m0a, m0b;
+    int fix_layer = 0, fix_pow = 0;   // rescaling of psi in the first reverse pass
+};
+int hbm_groups_of(int k);
+int hbm_group_qubits(int k, int grp);
+std::vector<PassSpec> hbm_program(int k, int p, bool grad);
+
 hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
                           double* energy, double* dgamma, double* dbeta, hipStream_t st);
 

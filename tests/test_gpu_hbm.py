@@ -1,0 +1,103 @@
+"""GPU parity of cones held in device memory (more than k_lds_max qubits) against the oracle.
+
+Same tolerances as test_gpu_parity.py.  Covered: two and three pass groups, depths 1-3,
+the p = 1 path that needs no state buffers, reduced plans, batching under a small memory
+budget, and agreement with the workgroup-resident kernel on 14-qubit cones.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from test_gpu_parity import ZZ_TOL, check_energy, dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2101_10296_amd as Q
+    return Q
+
+
+def test_hbm_matches_workgroup_kernel_on_14_qubit_cones(Q):
+    g = W.random_regular(30, 3, 5)
+    ga, be = W.draw_angles(5, 2, 3)
+    a = Q.Plan(g.n, g.edges, p=2)
+    b = Q.Plan(g.n, g.edges, p=2, k_lds_max=13)
+    assert b.info()["n_hbm_cones"] > 0
+    Ea, dga, dba = a.energy_grad(dev(ga), dev(be))
+    Eb, dgb, dbb = b.energy_grad(dev(ga), dev(be))
+    assert (Ea - Eb).abs().max().item() <= ZZ_TOL * g.m / 2
+    scale = max(dga.abs().max().item(), dba.abs().max().item())
+    assert (dga - dgb).abs().max().item() <= 1e-4 * scale
+    assert (dba - dbb).abs().max().item() <= 1e-4 * scale
+    check_energy(Q, g, 2, ga, be, reduce=False, grad=True, plan_kw=dict(k_lds_max=13))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_hbm_k14_all_depths(Q, p):
+    g = W.star(13)
+    ga, be = W.draw_angles(3, p, 70 + p)
+    check_energy(Q, g, p, ga, be, grad=True, plan_kw=dict(k_lds_max=13))
+
+
+def test_torus_k18_p2_reduced(Q):
+    g = W.torus2d(7)
+    ga, be = W.draw_angles(3, 2, 11)
+    pl, _, _ = check_energy(Q, g, 2, ga, be, grad=True)
+    assert pl.info()["max_k"] == 18 and pl.info()["n_orbits"] == 1
+
+
+def test_several_hbm_classes_one_plan(Q):
+    # C_60(1,2,3) at p = 2: three orbits with 14-, 15- and 16-qubit cones
+    g = W.circulant(60, (1, 2, 3))
+    ga, be = W.draw_angles(3, 2, 12)
+    pl, _, _ = check_energy(Q, g, 2, ga, be, grad=True)
+    assert pl.info()["n_hbm_cones"] == 2 and pl.info()["max_k"] == 16
+
+
+def test_hypercube_q10_p1_k20(Q):
+    g = W.hypercube(10)
+    ga, be = W.draw_angles(4, 1, 13)
+    pl, _, zz = check_energy(Q, g, 1, ga, be, grad=True)
+    assert pl.info()["max_k"] == 20
+
+
+def test_q12_p1_k24_closed_form(Q):
+    # config: hypercube Q_12, p = 1, one orbit, a 24-qubit cone; the p = 1 closed form
+    # gives zz, and central differences of it (FP64) give the gradient
+    (g, p), = W.workload("c5i")[0]
+    _, ga, be = W.workload("c5i")
+    pl = Q.Plan(g.n, g.edges, p=1, generators=g.gens())
+    assert pl.info()["max_k"] == 24 and pl.info()["n_orbits"] == 1
+    E, zz = pl.energy(dev(ga), dev(be), term_zz=True)
+    E2, dg, db = pl.energy_grad(dev(ga), dev(be))
+    u, v = (int(x) for x in g.edges[0])
+    cf = lambda a, b: oracle.zz_p1(g.n, g.edges, None, u, v, a, b)  # noqa: E731
+    h = 1e-6
+    for i in range(ga.shape[0]):
+        z = cf(ga[i, 0], be[i, 0])
+        assert abs(zz[i, 0].item() - z) <= ZZ_TOL
+        dz_g = (cf(ga[i, 0] + h, be[i, 0]) - cf(ga[i, 0] - h, be[i, 0])) / (2 * h)
+        dz_b = (cf(ga[i, 0], be[i, 0] + h) - cf(ga[i, 0], be[i, 0] - h)) / (2 * h)
+        ref = np.array([-0.5 * g.m * dz_g, -0.5 * g.m * dz_b])
+        got = np.array([dg[i, 0].item(), db[i, 0].item()])
+        assert np.abs(got - ref).max() <= 1e-4 * max(np.abs(ref).max(), 1e-3 * g.m)
+        assert abs(E2[i].item() - g.m * (1 - z) / 2) <= ZZ_TOL * g.m / 2
+
+
+def test_small_memory_budget_batches(Q):
+    g = W.torus2d(7)
+    ga, be = W.draw_angles(5, 2, 15)
+    full = Q.Plan(g.n, g.edges, p=2, reduce=False)
+    tight = Q.Plan(g.n, g.edges, p=2, reduce=False, mem_budget_bytes=3 * (8 << 18))
+    Ef, dgf, dbf = full.energy_grad(dev(ga), dev(be))
+    Et, dgt, dbt = tight.energy_grad(dev(ga), dev(be))
+    assert torch.equal(Ef, Et) and torch.equal(dgf, dgt) and torch.equal(dbf, dbt)
+    with pytest.raises(Q.QaoaError) as ei:
+        Q.Plan(g.n, g.edges, p=2, mem_budget_bytes=1 << 20).energy_grad(dev(ga), dev(be))
+    assert ei.value.status == Q.QAOA_ENOMEM

@@ -17,6 +17,7 @@ from .graphs import (  # noqa: F401
     triangle,
     single_edge,
     star,
+    spider_pair,
     relabel,
 )
 from .angles import draw_angles  # noqa: F401

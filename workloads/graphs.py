@@ -207,6 +207,49 @@ def star(m: int) -> Graph:
     return Graph(f"star{m}", n, _canon(n, e), generators=np.asarray(gens, np.int32).reshape(-1, n))
 
 
+def spider_pair(a: int, b: int) -> Graph:
+    """Two hubs 0 and 1 joined by an edge; hub 0 carries a legs of length 2, hub 1 carries b
+    legs of length 2, and the last leg of hub 1 ends in two leaves instead of one.
+
+    The radius-2 light cone of the edge (0, 1) holds 2 + 2a + 2b + 1 qubits; generators
+    permute the legs of each hub and swap the two forked leaves.
+    """
+    if a < 2 or b < 3:
+        raise ValueError("spider_pair needs a >= 2, b >= 3")
+    e = [(0, 1)]
+    nxt = 2
+    legs0, legs1 = [], []
+    for _ in range(a):
+        e += [(0, nxt), (nxt, nxt + 1)]
+        legs0.append((nxt, nxt + 1))
+        nxt += 2
+    for _ in range(b - 1):
+        e += [(1, nxt), (nxt, nxt + 1)]
+        legs1.append((nxt, nxt + 1))
+        nxt += 2
+    x = nxt
+    e += [(1, x), (x, x + 1), (x, x + 2)]
+    n = x + 3
+    i = np.arange(n)
+
+    def legs_swap(legs):          # exchange the first two legs
+        s = i.copy()
+        (c0, l0), (c1, l1) = legs[0], legs[1]
+        s[c0], s[l0], s[c1], s[l1] = c1, l1, c0, l0
+        return s
+
+    def legs_cycle(legs):         # leg j -> leg j + 1
+        s = i.copy()
+        for j, (c, l) in enumerate(legs):
+            s[c], s[l] = legs[(j + 1) % len(legs)]
+        return s
+
+    swap = i.copy()
+    swap[x + 1], swap[x + 2] = x + 2, x + 1
+    gens = [legs_swap(legs0), legs_cycle(legs0), legs_swap(legs1), legs_cycle(legs1), swap]
+    return Graph(f"spider{a},{b}", n, _canon(n, np.array(e)), generators=np.asarray(gens, np.int32))
+
+
 def single_edge() -> Graph:
     return Graph("K2", 2, np.array([[0, 1]], np.int32), generators=np.array([[1, 0]], np.int32))
 
