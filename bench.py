@@ -42,6 +42,28 @@ def flops_fwd_adj(k: int, p: int) -> float:
     return n * (fwd + adj)
 
 
+def hbm_groups(k: int) -> int:
+    """Pass groups of a k-qubit cone held in device memory: qubits 0..12, then nine at a time."""
+    return 1 + (k - 13 + 8) // 9
+
+
+def hbm_bytes_per_item(k: int, p: int, grad: bool) -> float:
+    """Algorithmic HBM bytes of one (cone, point) item of the device-memory pass program.
+
+    8 B per complex64 amplitude read or written.  Forward: the first pass writes the state,
+    every later pass reads and writes it, the final pass only reads it (with the gradient it
+    also writes lambda).  Reverse: every pass but the last reads and writes psi and lambda;
+    the last (undoing the first forward pass) only reads them.  p = 1 keeps no state.
+    """
+    if p == 1:
+        return 0.0
+    F = (p - 1) * (hbm_groups(k) - 1)   # passes after the first (k > 13: at least two groups)
+    n = float(1 << k)
+    if grad:
+        return n * (8 + 16 * (F - 1) + 16 + 16 + 32 * (F - 1))
+    return n * (8 + 16 * (F - 1) + 8)
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):

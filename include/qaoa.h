@@ -80,9 +80,9 @@ typedef struct {
     int32_t k_lds_max;            /* cones with k <= this run entirely inside one workgroup,
                                      larger ones as passes over tiles held in device memory
                                      (0 = default 14; 13 or 14) */
-    int32_t checkpoint_mode;      /* adjoint of cones held in HBM: 0 = uncompute (default:
-                                     the forward state is recovered by inverse layers),
-                                     1 = keep one state per pass when it fits the budget */
+    int32_t checkpoint_mode;      /* adjoint of cones held in HBM: must be 0 = uncompute (the
+                                     forward state is recovered by inverse layers, two live
+                                     states per item); any other value -> QAOA_EINVAL */
     int32_t one_cone_at_a_time;   /* 1 = plain GPU path: one launch per (cone, point) */
     int32_t profile;              /* 1 = record HIP events around every kernel group of each
                                      energy call (read with qaoa_plan_kernel_times) */

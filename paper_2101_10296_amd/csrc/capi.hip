@@ -46,7 +46,9 @@ qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* o
         o.profile = opts->profile;
         if (o.mem_budget_bytes < 0) return set_err(QAOA_EINVAL, "mem_budget_bytes must be >= 0");
         if (o.reduce != 0 && o.reduce != 1) return set_err(QAOA_EINVAL, "reduce must be 0 or 1");
-        if (o.checkpoint_mode != 0 && o.checkpoint_mode != 1) return set_err(QAOA_EINVAL, "checkpoint_mode must be 0 or 1");
+        if (o.checkpoint_mode != 0)
+            return set_err(QAOA_EINVAL, "checkpoint_mode must be 0: the adjoint recovers forward states by inverse "
+                                        "layers; stored per-pass states are not provided");
     }
     try {
         auto* plan = new qaoa_plan_s();

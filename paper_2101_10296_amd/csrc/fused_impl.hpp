@@ -7,7 +7,7 @@
 // tau in register r has basis index q = rotl_K((tau << AB) | r, st * AB): the AB
 // register bits cover qubits st*AB .. st*AB+AB-1, so the single-qubit mixers of those
 // qubits are butterflies between registers.  Moving between stages is a transpose
-// through LDS (XOR-swizzled against bank conflicts).  Layers alternate the stage order
+// through LDS (padded against bank conflicts).  Layers alternate the stage order
 // so that consecutive layers share a stage and the last full layer ends in stage 0,
 // which holds qubits 0 and 1 (u and v) for the final two-qubit mixer and <Z_0 Z_1>.
 //

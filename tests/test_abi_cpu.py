@@ -114,6 +114,14 @@ def test_error_codes(bad, status):
     assert len(str(ei.value)) > len("QAOA_EINVAL: ")
 
 
+@pytest.mark.parametrize("opts", [dict(checkpoint_mode=1), dict(k_lds_max=12), dict(k_lds_max=15),
+                                  dict(max_cone_qubits=31), dict(mem_budget_bytes=-1)])
+def test_option_errors(opts):
+    with pytest.raises(Q.QaoaError) as ei:
+        Q.Plan(3, [[0, 1], [1, 2]], p=1, **opts)
+    assert ei.value.status == Q.QAOA_EINVAL
+
+
 def test_cut_range_limit():
     # 3 x 3 rook graph with weight 30 per edge: cut values span more than 255 integers
     g = W.rook(3)

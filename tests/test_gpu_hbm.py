@@ -101,3 +101,37 @@ def test_small_memory_budget_batches(Q):
     with pytest.raises(Q.QaoaError) as ei:
         Q.Plan(g.n, g.edges, p=2, mem_budget_bytes=1 << 20).energy_grad(dev(ga), dev(be))
     assert ei.value.status == Q.QAOA_ENOMEM
+
+
+def _golden_cases():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_cases.json")
+    with open(path) as f:
+        return {c["name"]: c for c in json.load(f)["cases"]}
+
+
+@pytest.mark.parametrize("name", ["spider5_5_p2", "C60_1_2_3_p3"])
+def test_stored_oracle_cases(Q, name):
+    # spider5_5_p2: a 23-qubit cone in three pass groups (every pass kind, both snake
+    # directions); C60_1_2_3_p3: 20-22-qubit cones at p = 3.  Oracle values stored by
+    # tests/golden/make_oracle_golden.py.
+    c = _golden_cases()[name]
+    g = getattr(W, c["family"])(*c["args"])
+    ga, be = W.draw_angles(c["points"], c["p"], c["seed"])
+    pl = Q.Plan(g.n, g.edges, p=c["p"], generators=g.gens() if c["reduce"] else None, reduce=c["reduce"])
+    eo, rep, _ = pl.orbits()
+    assert list(rep) == c["rep"]
+    E, zz = pl.energy(dev(ga), dev(be), term_zz=True)
+    E2, dg, db = pl.energy_grad(dev(ga), dev(be))
+    zz = zz.cpu().numpy()
+    Wt = float(np.sum(c["W"]))
+    assert np.abs(zz - np.array(c["zz"])).max() <= ZZ_TOL
+    assert np.abs(E.cpu().numpy() - np.array(c["energy"])).max() <= ZZ_TOL * Wt / 2
+    assert np.abs(E2.cpu().numpy() - np.array(c["energy"])).max() <= ZZ_TOL * Wt / 2
+    dgo, dbo = np.array(c["dgamma"]), np.array(c["dbeta"])
+    dg, db = dg.cpu().numpy(), db.cpu().numpy()
+    for i in range(ga.shape[0]):
+        ref_inf = max(np.abs(dgo[i]).max(), np.abs(dbo[i]).max())
+        err = max(np.abs(dg[i] - dgo[i]).max(), np.abs(db[i] - dbo[i]).max())
+        assert err <= 1e-4 * max(ref_inf, 1e-3 * Wt), (i, err, ref_inf)
