@@ -104,6 +104,57 @@ def oracle_baseline(graphs, ga, be, budget_s: float):
     return 1.0 / total * len(graphs), "; ".join(desc)
 
 
+def hbm_measure(Q, torch, W, points: int) -> dict:
+    """Large cones: random 3-regular n=200 at p=3 (300 cones of 20-30 qubits), energy and
+    gradient at the first `points` angle points, through the device-memory pass kernels.
+
+    achieved = algorithmic state bytes (hbm_bytes_per_item x items, summed over cone sizes)
+    over the HIP-event time of those kernel groups (passes, zero fill and tile reductions).
+    """
+    (g, p), = W.workload("c5ii")[0]
+    _, ga, be = W.workload("c5ii")
+    gt = torch.tensor(ga[:points], dtype=torch.float64, device="cuda")
+    bt = torch.tensor(be[:points], dtype=torch.float64, device="cuda")
+    pl = Q.Plan(g.n, g.edges, p=p, profile=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.energy_grad(gt, bt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    byts, ms, by_k = 0.0, 0.0, {}
+    for k, items, t in pl.kernel_times():
+        if k > 14:
+            b = hbm_bytes_per_item(k, p, True) * items
+            byts += b
+            ms += t
+            by_k[k] = round(b / (t * 1e-3) / 1e9, 1)
+    pl.close()
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": f"random 3-regular n=200 (seed 502), p=3, {points} point(s), energy+gradient, "
+                        "300 cones of 20-30 qubits in device memory",
+            "evals_per_s": round(points / wall, 4), "wall_s": round(wall, 3),
+            "kernel_ms": round(ms, 2), "algorithmic_GB": round(byts / 1e9, 2),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+            "achieved_GBps_by_k": by_k}
+
+
+def copy_measure(torch, gib: float) -> dict:
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"bytes_each_way": n * 4, "ms": round(ms, 3), "GBps_read_plus_write": round(2 * n * 4 / ms / 1e6, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +163,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--hbm-points", type=int, default=1,
+                    help="angle points of the large-cone (device-memory) measurement; 0 = skip")
+    ap.add_argument("--hbm-only", action="store_true", help="only the large-cone measurement")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="also time a device-to-device copy of this many GiB (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -120,6 +176,13 @@ def main():
     import torch
     import paper_2101_10296_amd as Q
     import workloads as W
+
+    if a.hbm_only:
+        out = {"hbm": hbm_measure(Q, torch, W, max(a.hbm_points, 1))}
+        if a.copy_gib > 0:
+            out["copy"] = copy_measure(torch, a.copy_gib)
+        print(json.dumps(out), flush=True)
+        return
 
     (g1, p), = W.workload("c2i")[0]
     (g2, _), = W.workload("c2ii")[0]
@@ -217,6 +280,8 @@ def main():
         "roofline": roofline,
     }
     line.update(extra)
+    if a.hbm_points > 0:
+        line["hbm"] = hbm_measure(Q, torch, W, a.hbm_points)
     if not a.no_cpu_baseline:
         v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
         line["cpu_baseline"] = {"value": round(v, 6), "unit": "evals/s", "cores": 1, "kind": "oracle",
