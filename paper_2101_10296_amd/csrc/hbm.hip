@@ -64,11 +64,14 @@ k_tile_reduce(const ConeHbm* __restrict__ cones, const double* __restrict__ gpar
     }
 }
 
+// Each workgroup walks pa.tpw consecutive tiles of one item (set-up once per item, one
+// block reduction per workgroup); the caller picks tpw.
 template <int KIND, bool G0>
 static hipError_t launch_one(const PassArgs& pa, hipStream_t st) {
     constexpr bool GR = KIND >= GR_GEN_FINAL;
     const int64_t tiles = int64_t{1} << (pa.k - HT);
-    const int64_t blocks = tiles * pa.n_batch;
+    if (pa.tpw < 1 || tiles % pa.tpw != 0) return hipErrorInvalidValue;
+    const int64_t blocks = tiles * pa.n_batch / pa.tpw;
     const size_t dyn = static_cast<size_t>(pa.ea.p) * pa.rowcap * sizeof(float2);
     hipLaunchKernelGGL((k_pass<KIND, G0>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<GR>::W), dyn, st, pa);
     return hipGetLastError();

@@ -80,14 +80,33 @@ struct PassArgs {
     int32_t rowcap;            // phase row capacity (largest cut range)
     int32_t fix_layer;         // > 0: the loaded psi is rescaled by |kappa_fix_layer|^fix_pow
     int32_t fix_pow;
+    int32_t tpw;               // tiles per workgroup (a power of two dividing the tile count)
     EvalArgs ea;
 };
 
+// Tuning (measured on MI355X over 20-30-qubit cones): register bits per thread and the
+// minimum waves per SIMD the compiler must allow.  Forward passes: 32 amplitudes per
+// thread, 256 threads; adjoint passes (two states): 16 per state, 512 threads, at most 128
+// registers so that two workgroups share a CU (LDS allows two).
+#ifndef QAOA_HBM_AB_FWD
+#define QAOA_HBM_AB_FWD 5
+#endif
+#ifndef QAOA_HBM_AB_GR
+#define QAOA_HBM_AB_GR 4
+#endif
+#ifndef QAOA_HBM_WPE_FWD
+#define QAOA_HBM_WPE_FWD 2
+#endif
+#ifndef QAOA_HBM_WPE_GR
+#define QAOA_HBM_WPE_GR 4
+#endif
+
 template <bool GR>
 struct Hz {
-    static constexpr int AB = GR ? 4 : 5;
+    static constexpr int AB = GR ? QAOA_HBM_AB_GR : QAOA_HBM_AB_FWD;
     static constexpr int A = 1 << AB;
     static constexpr int W = 1 << (HT - AB);        // threads per tile
+    static constexpr int WPE = GR ? QAOA_HBM_WPE_GR : QAOA_HBM_WPE_FWD;   // minimum waves per SIMD
     static constexpr uint32_t NPAD = HN + (HN >> 5) + (HN >> 10);
     static constexpr int ROT_IO0 = HT - AB;          // I/O layout of group 0: lanes on tile bits 0..5
     static constexpr int ROT_IOJ = 9 - AB;           // I/O layout of groups >= 1: lanes on tile bits 9..12, 0, 1
@@ -237,79 +256,44 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 }
 
 template <int KIND, bool G0>
-__global__ void __launch_bounds__((Hz<(KIND >= GR_GEN_FINAL)>::W))
+__global__ void __launch_bounds__((Hz<(KIND >= GR_GEN_FINAL)>::W), (Hz<(KIND >= GR_GEN_FINAL)>::WPE))
 k_pass(PassArgs pa) {
     constexpr bool GR = KIND >= GR_GEN_FINAL;
     using H = Hz<GR>;
     using HS = HStages<GR, G0>;
     constexpr int A = H::A;
     constexpr int NW = (A + 3) / 4;
-    constexpr bool GEN = (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL);
     constexpr bool FINAL = (KIND == FWD_GEN_FINAL || KIND == FWD_BND_FINAL || KIND == GR_GEN_FINAL ||
                             KIND == GR_BND_FINAL);
     __shared__ float2 xbuf[H::NPAD];
     __shared__ __attribute__((aligned(16))) uint8_t ttl[HN];
-    __shared__ uint32_t gstr[HT];
     __shared__ int32_t lcoef[HT];
     __shared__ double red[H::W / 64];
     __shared__ int32_t k0_sh;
+    __shared__ int8_t tpos[32];          // tile bit of each global bit, -1 outside the tile
     extern __shared__ float2 rows[];   // [p][rowcap]
 
     const int tid = threadIdx.x;
     const uint32_t tau = static_cast<uint32_t>(tid);
     const int k = pa.k;
     const int64_t tiles = int64_t{1} << (k - HT);
-    const int64_t bslot = blockIdx.x / tiles;             // item within the batch
-    const int64_t tile = blockIdx.x - bslot * tiles;
+    const int64_t wpi = tiles / pa.tpw;                   // workgroups per item
+    const int64_t bslot = blockIdx.x / wpi;               // item within the batch
+    const int64_t tile0 = (blockIdx.x - bslot * wpi) * pa.tpw;
     const int64_t item = pa.item0 + bslot;
     const int P = pa.ea.P, p = pa.ea.p;
     const int64_t cslot = item / P;
     const int point = static_cast<int>(item - cslot * P);
     const ConeHbm cd = pa.cones[cslot];
 
-    // ---- group geometry, outer bits, and the linear cut coefficients of this tile
+    // ---- per-item set-up: group geometry, C_tt table, phase rows
     int h = 0;
     uint32_t tmask = 0;  // global bits inside the tile
     for (int i = 0; i < HT; ++i) tmask |= 1u << hgroup_bits(k, pa.group, i, h);
-    uint64_t xo = 0;     // global index bits of the tile's outer part
-    {
-        int64_t o = tile;
-        for (int b = 0; b < k; ++b)
-            if (!((tmask >> b) & 1u)) {
-                xo |= static_cast<uint64_t>(o & 1) << b;
-                o >>= 1;
-            }
-    }
     const uint32_t pm = (pa.group == 0) ? (HN - 1u) : ((1u << h) - 1u);
-    if (tid < HT) {
-        int hh;
-        const int gb = hgroup_bits(k, pa.group, tid, hh);
-        gstr[tid] = 1u << gb;
-        // WO_b - 2 W1_b for tile bit tid
-        int32_t wo = 0, w1 = 0;
-        for (int e = 0; e < cd.n_edges; ++e) {
-            const int a = pa.e_a[cd.edge_off + e], b = pa.e_b[cd.edge_off + e], w = pa.e_w[cd.edge_off + e];
-            const int other = (a == gb) ? b : ((b == gb) ? a : -1);
-            if (other >= 0 && !((tmask >> other) & 1u)) {
-                wo += w;
-                if ((xo >> other) & 1u) w1 += w;
-            }
-        }
-        lcoef[tid] = wo - 2 * w1;
-    }
-    if (tid == 0) {   // C_oo(o) + sum_b W1_b
-        int32_t c = 0;
-        for (int e = 0; e < cd.n_edges; ++e) {
-            const int a = pa.e_a[cd.edge_off + e], b = pa.e_b[cd.edge_off + e], w = pa.e_w[cd.edge_off + e];
-            const bool ia = (tmask >> a) & 1u, ib = (tmask >> b) & 1u;
-            const int xa = static_cast<int>((xo >> a) & 1u), xb2 = static_cast<int>((xo >> b) & 1u);
-            if (!ia && !ib) c += w * (xa ^ xb2);
-            else if (ia && !ib) c += w * xb2;
-            else if (!ia && ib) c += w * xa;
-        }
-        k0_sh = c + pa.cones[cslot].tt_min[pa.group] - cd.cut_min;
-    }
-    {   // C_tt table and the phase rows of this item
+    const int32_t k0_base = pa.cones[cslot].tt_min[pa.group] - cd.cut_min;
+    if (tid < 32) tpos[tid] = -1;
+    {
         const uint8_t* src = pa.tt + pa.cones[cslot].tt_off[pa.group];
         for (uint32_t q = tau * 16; q < HN; q += H::W * 16)
             *reinterpret_cast<uint4*>(ttl + q) = *reinterpret_cast<const uint4*>(src + q);
@@ -319,197 +303,274 @@ k_pass(PassArgs pa) {
                 rows[l * pa.rowcap + c] = ph0[static_cast<size_t>(l) * pa.ea.R + c];
     }
     __syncthreads();
-    float2* xb = xbuf;
-    const float2* mix0 = pa.ea.mix + static_cast<size_t>(point) * p;
-    auto kpowK = [&](float k2) { return exp2f(0.5f * k * log2f(k2)); };
-    const float k2p = mix0[p - 1].y;
-
-    // packed cut values (minus cut_min) of the thread's amplitudes in layout rotation 0
-    uint32_t pk0[NW];
-    {
-        const uint32_t qb = htbase<GR, 0>(tau);
-        int32_t lthr = k0_sh;
-#pragma unroll
-        for (int i = 0; i < HT; ++i)
-            if ((qb >> i) & 1u) lthr += lcoef[i];
-#pragma unroll
-        for (int w2 = 0; w2 < NW; ++w2) pk0[w2] = 0u;
-#pragma unroll
-        for (int r = 0; r < A; ++r) {
-            int32_t c = lthr + ttl[qb | hroff<GR, 0>(r)];
-#pragma unroll
-            for (int i = 0; i < H::AB; ++i)
-                if ((r >> i) & 1) c += lcoef[i];
-            pk0[r >> 2] |= static_cast<uint32_t>(c) << (8 * (r & 3));
-        }
+    if (tid < HT) {
+        int hh;
+        tpos[hgroup_bits(k, pa.group, tid, hh)] = static_cast<int8_t>(tid);
+    }
+    // the thread's first cone edge, kept in registers for every tile
+    int e0a = 0, e0b = 0, e0w = 0;
+    if (tid < cd.n_edges) {
+        e0a = pa.e_a[cd.edge_off + tid];
+        e0b = pa.e_b[cd.edge_off + tid];
+        e0w = pa.e_w[cd.edge_off + tid];
     }
 
-    // ---- global addressing of the I/O layout
+    // ---- global addressing of the I/O layout.  The global bit of every tile bit depends
+    // only on (k, group), so the per-register offsets are uniform (scalar registers); only
+    // the thread's own offset lives in a vector register.
     constexpr int RIO = HS::IO;
+    uint32_t gbit[HT];
+#pragma unroll
+    for (int i = 0; i < HT; ++i) {
+        int hh;
+        gbit[i] = static_cast<uint32_t>(hgroup_bits(k, pa.group, i, hh));
+    }
     const uint32_t qio = htbase<GR, RIO>(tau);
-    uint64_t gbase = xo;
+    // the thread's byte offset: its bits sit at most at global bit 26 (group 0: 12), so
+    // it fits 32 bits and the loads use a scalar base plus a 32-bit vector offset
+    uint32_t tbyte = 0;
 #pragma unroll
     for (int i = 0; i < HT; ++i)
-        if ((qio >> i) & 1u) gbase += gstr[i];
-    const size_t item_off = static_cast<size_t>(bslot) << k;
+        if ((qio >> i) & 1u) tbyte += 8u << gbit[i];
     auto io_off = [&](int r) -> uint64_t {
         uint64_t o = 0;
         const uint32_t q = hroff<GR, RIO>(r);
 #pragma unroll
         for (int i = 0; i < HT; ++i)
-            if ((q >> i) & 1u) o += gstr[i];
+            if ((q >> i) & 1u) o += uint64_t{1} << gbit[i];
         return o;
     };
-    auto load = [&](float2 (&v)[A], const float2* buf) {
-        const float2* b = buf + item_off + gbase;
+    // (the thread offset is made opaque at every use so that no per-register address is
+    // computed ahead and held in vector registers)
+    auto load = [&](float2 (&v)[A], const float2* buf, size_t item_off) {
+        const uint32_t tb = opaque_u32(tbyte);
 #pragma unroll
-        for (int r = 0; r < A; ++r) v[r] = b[io_off(r)];
+        for (int r = 0; r < A; ++r)
+            v[r] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(buf + item_off + io_off(r)) + tb);
     };
-    auto store = [&](const float2 (&v)[A], float2* buf) {
-        float2* b = buf + item_off + gbase;
+    auto store = [&](const float2 (&v)[A], float2* buf, size_t item_off) {
+        const uint32_t tb = opaque_u32(tbyte);
 #pragma unroll
-        for (int r = 0; r < A; ++r) b[io_off(r)] = v[r];
+        for (int r = 0; r < A; ++r)
+            *reinterpret_cast<float2*>(reinterpret_cast<char*>(buf + item_off + io_off(r)) + tb) = v[r];
     };
-    double* gp = pa.gpart + (static_cast<size_t>(bslot) * tiles + tile) * (2 * p + 1);
-
-    float2 f[A];
+    float2* xb = xbuf;
+    const float2* mix0 = pa.ea.mix + static_cast<size_t>(point) * p;
+    auto kpowK = [&](float k2) { return exp2f(0.5f * k * log2f(k2)); };
+    const float k2p = mix0[p - 1].y;
     constexpr int RL = HS::rot(HS::S - 1);   // last processing layout
-    // ---------------------------------------------------------------- forward part
-    if constexpr (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL) {
-        gen_stage(f, pk0, rows, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
-        if constexpr (KIND == FWD_GEN_MIX) {
-            hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[0].x, pm);
-            hxpose<GR, RL, RIO>(f, xb, tau);
-            store(f, pa.phi);
-            return;
-        }
+
+    // Per-thread partial sums over the workgroup's tiles, reduced once at the end into the
+    // slot of (item, first tile): [0] = zz, [1 + l - 1] = d/d gamma_l, [1 + p + l - 1] =
+    // d/d beta_l.  Which partial goes to which slot depends on the pass kind.
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    int slot[4] = {-1, -1, -1, -1};
+    if constexpr (KIND == FWD_GEN_FINAL || KIND == FWD_BND_FINAL) {
+        slot[0] = 0;
+    } else if constexpr (KIND == GR_GEN_FINAL) {
+        slot[0] = 0; slot[1] = 2 * p; slot[2] = 1;
+    } else if constexpr (KIND == GR_BND_FINAL) {
+        slot[0] = 0; slot[1] = 2 * p; slot[2] = p; slot[3] = p + pa.la;
+    } else if constexpr (KIND == RV_MIX) {
+        slot[0] = p + pa.la;
+    } else if constexpr (KIND == RV_GEN_MIX) {
+        slot[0] = p + pa.lb; slot[1] = 1;
+    } else if constexpr (KIND == RV_BND_MIX) {
+        slot[0] = p + pa.lb; slot[1] = pa.lb; slot[2] = p + pa.la;
     }
-    if constexpr (KIND == FWD_MIX || KIND == FWD_BND_MIX || KIND == FWD_BND_FINAL || KIND == GR_BND_FINAL) {
-        load(f, pa.phi);
-        const float2 tka = mix0[pa.la - 1];
-        hmix_group<GR, G0, true, RIO>(f, xb, tau, tka.x, pm);     // ends in rotation 0
-        if constexpr (KIND == FWD_MIX) {
-            hxpose<GR, 0, RIO>(f, xb, tau);
-            store(f, pa.phi);
-            return;
+
+    for (int64_t tile = tile0; tile < tile0 + pa.tpw; ++tile) {
+        // ---- outer bits of this tile and its linear cut coefficients: an edge between tile
+        // bit b and an outer bit o adds w (1 - 2 x_o) to lcoef[b] and w x_o to k0; an edge
+        // between two outer bits adds w (x_o1 xor x_o2) to k0 (integer atomics: exact in
+        // any order)
+        uint64_t xo = 0;
+        {
+            int64_t o = tile;
+            for (int b = 0; b < k; ++b)
+                if (!((tmask >> b) & 1u)) {
+                    xo |= static_cast<uint64_t>(o & 1) << b;
+                    o >>= 1;
+                }
         }
-        phase_stage(f, pk0, rows + (pa.lb - 1) * pa.rowcap, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
-        if constexpr (KIND == FWD_BND_MIX) {
-            hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[pa.lb - 1].x, pm);
-            hxpose<GR, RL, RIO>(f, xb, tau);
-            store(f, pa.phi);
-            return;
+        __syncthreads();   // the previous tile has read lcoef and k0
+        if (tid < HT) lcoef[tid] = 0;
+        if (tid == 0) k0_sh = k0_base;
+        __syncthreads();
+        auto add_edge = [&](int a, int b, int w) {
+            const int ia = tpos[a], ib = tpos[b];
+            const int xa = static_cast<int>((xo >> a) & 1u), xb2 = static_cast<int>((xo >> b) & 1u);
+            if (ia >= 0 && ib < 0) {
+                atomicAdd(&lcoef[ia], w - 2 * w * xb2);
+                if (xb2) atomicAdd(&k0_sh, w);
+            } else if (ia < 0 && ib >= 0) {
+                atomicAdd(&lcoef[ib], w - 2 * w * xa);
+                if (xa) atomicAdd(&k0_sh, w);
+            } else if (ia < 0 && ib < 0 && (xa ^ xb2)) {
+                atomicAdd(&k0_sh, w);
+            }
+        };
+        if (tid < cd.n_edges) add_edge(e0a, e0b, e0w);
+        for (int e = tid + H::W; e < cd.n_edges; e += H::W)
+            add_edge(pa.e_a[cd.edge_off + e], pa.e_b[cd.edge_off + e], pa.e_w[cd.edge_off + e]);
+        __syncthreads();
+
+        // packed cut values (minus cut_min) of the thread's amplitudes in layout rotation 0
+        uint32_t pk0[NW];
+        {
+            const uint32_t qb = htbase<GR, 0>(tau);
+            int32_t lthr = k0_sh;
+#pragma unroll
+            for (int i = 0; i < HT; ++i)
+                if ((qb >> i) & 1u) lthr += lcoef[i];
+#pragma unroll
+            for (int w2 = 0; w2 < NW; ++w2) pk0[w2] = 0u;
+#pragma unroll
+            for (int r = 0; r < A; ++r) {
+                int32_t c = lthr + ttl[qb | hroff<GR, 0>(r)];
+#pragma unroll
+                for (int i = 0; i < H::AB; ++i)
+                    if ((r >> i) & 1) c += lcoef[i];
+                pk0[r >> 2] |= static_cast<uint32_t>(c) << (8 * (r & 3));
+            }
         }
-    }
-    // ---------------------------------------------------------------- final layer
-    if constexpr (FINAL) {
-        const float tp = mix0[p - 1].x;
-#pragma unroll
-        for (int r = 0; r < A; ++r)
-            if (!(r & 1)) bfly(f[r], f[r | 1], tp);
-#pragma unroll
-        for (int r = 0; r < A; ++r)
-            if (!(r & 2)) bfly(f[r], f[r | 2], tp);
-        double zzp = 0.0;
-#pragma unroll
-        for (int r = 0; r < A; ++r) {
-            const double pr = static_cast<double>(fmaf(f[r].x, f[r].x, f[r].y * f[r].y));
-            zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
+        const size_t item_off = (static_cast<size_t>(bslot) << k) + xo;
+
+        float2 f[A];
+        // ------------------------------------------------------------ forward part
+        if constexpr (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL) {
+            gen_stage(f, pk0, rows, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
+            if constexpr (KIND == FWD_GEN_MIX) {
+                hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[0].x, pm);
+                hxpose<GR, RL, RIO>(f, xb, tau);
+                store(f, pa.phi, item_off);
+                continue;
+            }
         }
-        const double zz = block_sum<H::W>(zzp, red);
-        if (tid == 0) gp[0] = zz;
-        if constexpr (GR) {
+        if constexpr (KIND == FWD_MIX || KIND == FWD_BND_MIX || KIND == FWD_BND_FINAL || KIND == GR_BND_FINAL) {
+            load(f, pa.phi, item_off);
+            const float2 tka = mix0[pa.la - 1];
+            hmix_group<GR, G0, true, RIO>(f, xb, tau, tka.x, pm);     // ends in rotation 0
+            if constexpr (KIND == FWD_MIX) {
+                hxpose<GR, 0, RIO>(f, xb, tau);
+                store(f, pa.phi, item_off);
+                continue;
+            }
+            phase_stage(f, pk0, rows + (pa.lb - 1) * pa.rowcap, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
+            if constexpr (KIND == FWD_BND_MIX) {
+                hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[pa.lb - 1].x, pm);
+                hxpose<GR, RL, RIO>(f, xb, tau);
+                store(f, pa.phi, item_off);
+                continue;
+            }
+        }
+        // ------------------------------------------------------------ final layer
+        if constexpr (FINAL) {
+            const float tp = mix0[p - 1].x;
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 1)) bfly(f[r], f[r | 1], tp);
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 2)) bfly(f[r], f[r | 2], tp);
+            double zzp = 0.0;
+#pragma unroll
+            for (int r = 0; r < A; ++r) {
+                const double pr = static_cast<double>(fmaf(f[r].x, f[r].x, f[r].y * f[r].y));
+                zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
+            }
+            part[0] += zzp;
+            if constexpr (GR) {
+                float2 lm[A];
+#pragma unroll
+                for (int r = 0; r < A; ++r) lm[r] = (((r ^ (r >> 1)) & 1) ? make_float2(-f[r].x, -f[r].y) : f[r]);
+                float acc = 0.f;
+#pragma unroll
+                for (int r = 0; r < A; ++r)
+                    if (!(r & 1)) xacc(acc, lm[r], lm[r | 1], f[r], f[r | 1]);
+#pragma unroll
+                for (int r = 0; r < A; ++r)
+                    if (!(r & 2)) xacc(acc, lm[r], lm[r | 2], f[r], f[r | 2]);
+                part[1] += 2.0 * static_cast<double>(acc);
+#pragma unroll
+                for (int r = 0; r < A; ++r)
+                    if (!(r & 2)) { bfly(f[r], f[r | 2], -tp); bfly(lm[r], lm[r | 2], -tp); }
+#pragma unroll
+                for (int r = 0; r < A; ++r)
+                    if (!(r & 1)) { bfly(f[r], f[r | 1], -tp); bfly(lm[r], lm[r | 1], -tp); }
+                const float mu = k2p;
+                if constexpr (KIND == GR_GEN_FINAL) {
+                    const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
+                    part[2] += 2.0 * static_cast<double>(mu) * mu * a;
+                } else {
+                    const float a = cgrad_stage<true>(f, lm, pk0, rows + (p - 1) * pa.rowcap, cd.cut_min, mu);
+                    part[2] += 2.0 * static_cast<double>(mu) * mu * a;
+                    // undo mixer la = p-1 on this group (state sits in rotation 0)
+                    const float2 tka = mix0[pa.la - 1];
+                    float w = exp2f(pa.m0a * log2f(tka.y));
+                    const float b = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, w, pm);
+                    part[3] += 2.0 * static_cast<double>(b);
+                    hxpose<GR, RL, RIO>(lm, xb, tau);
+                    store(lm, pa.lam, item_off);
+                }
+            }
+        }
+        // ------------------------------------------------------------ reverse passes
+        if constexpr (KIND == RV_GEN_MIX || KIND == RV_MIX || KIND == RV_BND_MIX) {
             float2 lm[A];
+            load(f, pa.phi, item_off);
+            load(lm, pa.lam, item_off);
+            if (pa.fix_layer > 0) {
+                // The first reverse pass reads psi as the forward sweep left it: the final pass
+                // mixed layer p-1 on group 0 (13 qubits) forward but lambda has undone them,
+                // and the factored mixer scales by 1/|kappa| per qubit in both directions, so
+                // psi carries |kappa|^(k-13) where lambda carries |kappa|^13.
+                const float sc = exp2f(0.5f * pa.fix_pow * log2f(mix0[pa.fix_layer - 1].y));
 #pragma unroll
-            for (int r = 0; r < A; ++r) lm[r] = (((r ^ (r >> 1)) & 1) ? make_float2(-f[r].x, -f[r].y) : f[r]);
-            float acc = 0.f;
-#pragma unroll
-            for (int r = 0; r < A; ++r)
-                if (!(r & 1)) xacc(acc, lm[r], lm[r | 1], f[r], f[r | 1]);
-#pragma unroll
-            for (int r = 0; r < A; ++r)
-                if (!(r & 2)) xacc(acc, lm[r], lm[r | 2], f[r], f[r | 2]);
-            const double gbp = block_sum<H::W>(2.0 * static_cast<double>(acc), red);
-            if (tid == 0) gp[1 + p + p - 1] = gbp;
-#pragma unroll
-            for (int r = 0; r < A; ++r)
-                if (!(r & 2)) { bfly(f[r], f[r | 2], -tp); bfly(lm[r], lm[r | 2], -tp); }
-#pragma unroll
-            for (int r = 0; r < A; ++r)
-                if (!(r & 1)) { bfly(f[r], f[r | 1], -tp); bfly(lm[r], lm[r | 1], -tp); }
-            const float mu = k2p;
-            if constexpr (KIND == GR_GEN_FINAL) {
-                const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
-                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
-                if (tid == 0) gp[1] = gc;
-            } else {
-                const float a = cgrad_stage<true>(f, lm, pk0, rows + (p - 1) * pa.rowcap, cd.cut_min, mu);
-                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
-                if (tid == 0) gp[1 + p - 1] = gc;
-                // undo mixer la = p-1 on this group (state sits in rotation 0)
+                for (int r = 0; r < A; ++r) f[r] = make_float2(sc * f[r].x, sc * f[r].y);
+            }
+            if constexpr (KIND == RV_MIX) {
                 const float2 tka = mix0[pa.la - 1];
                 float w = exp2f(pa.m0a * log2f(tka.y));
-                const float b = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, w, pm);
-                const double gb = block_sum<H::W>(2.0 * static_cast<double>(b), red);
-                if (tid == 0) gp[1 + p + pa.la - 1] += gb;
-                hxpose<GR, RL, RIO>(lm, xb, tau);
-                store(lm, pa.lam);
-            }
-        }
-    }
-    // ---------------------------------------------------------------- reverse passes
-    if constexpr (KIND == RV_GEN_MIX || KIND == RV_MIX || KIND == RV_BND_MIX) {
-        float2 lm[A];
-        load(f, pa.phi);
-        load(lm, pa.lam);
-        if (pa.fix_layer > 0) {
-            // The first reverse pass reads psi as the forward sweep left it: the final pass
-            // mixed layer p-1 on group 0 (13 qubits) forward but lambda has undone them, and
-            // the factored mixer scales by 1/|kappa| per qubit in both directions, so psi
-            // carries |kappa|^(k-13) where lambda carries |kappa|^13.
-            const float sc = exp2f(0.5f * pa.fix_pow * log2f(mix0[pa.fix_layer - 1].y));
-#pragma unroll
-            for (int r = 0; r < A; ++r) f[r] = make_float2(sc * f[r].x, sc * f[r].y);
-        }
-        if constexpr (KIND == RV_MIX) {
-            const float2 tka = mix0[pa.la - 1];
-            float w = exp2f(pa.m0a * log2f(tka.y));
-            const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tka.x, tka.y, w, pm);
-            const double gb = block_sum<H::W>(2.0 * static_cast<double>(b), red);
-            if (tid == 0) gp[1 + p + pa.la - 1] += gb;
-            hxpose<GR, 0, RIO>(f, xb, tau);
-            hxpose<GR, 0, RIO>(lm, xb, tau);
-            store(f, pa.phi);
-            store(lm, pa.lam);
-        } else {
-            // undo mixer lb (the first group of layer lb in forward order: after it, layer lb
-            // is completely undone), then gamma_lb
-            const float2 tkb = mix0[pa.lb - 1];
-            float w = exp2f(pa.m0b * log2f(tkb.y));
-            const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tkb.x, tkb.y, w, pm);
-            const double gb = block_sum<H::W>(2.0 * static_cast<double>(b), red);
-            if (tid == 0) gp[1 + p + pa.lb - 1] += gb;
-            const float mu = (pa.lb == p) ? k2p : kpowK(tkb.y);
-            if constexpr (KIND == RV_GEN_MIX) {
-                const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
-                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
-                if (tid == 0) gp[1] += gc;
+                const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tka.x, tka.y, w, pm);
+                part[0] += 2.0 * static_cast<double>(b);
+                hxpose<GR, 0, RIO>(f, xb, tau);
+                hxpose<GR, 0, RIO>(lm, xb, tau);
+                store(f, pa.phi, item_off);
+                store(lm, pa.lam, item_off);
             } else {
-                const float a = cgrad_stage<true>(f, lm, pk0, rows + (pa.lb - 1) * pa.rowcap, cd.cut_min, mu);
-                const double gc = block_sum<H::W>(2.0 * static_cast<double>(mu) * mu * a, red);
-                if (tid == 0) gp[1 + pa.lb - 1] += gc;
-                const float2 tka = mix0[pa.la - 1];
-                float wa = exp2f(pa.m0a * log2f(tka.y));
-                const float ba = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, wa, pm);
-                const double gba = block_sum<H::W>(2.0 * static_cast<double>(ba), red);
-                if (tid == 0) gp[1 + p + pa.la - 1] += gba;
-                hxpose<GR, RL, RIO>(f, xb, tau);
-                hxpose<GR, RL, RIO>(lm, xb, tau);
-                store(f, pa.phi);
-                store(lm, pa.lam);
+                // undo mixer lb (the first group of layer lb in forward order: after it, layer
+                // lb is completely undone), then gamma_lb
+                const float2 tkb = mix0[pa.lb - 1];
+                float w = exp2f(pa.m0b * log2f(tkb.y));
+                const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tkb.x, tkb.y, w, pm);
+                part[0] += 2.0 * static_cast<double>(b);
+                const float mu = (pa.lb == p) ? k2p : kpowK(tkb.y);
+                if constexpr (KIND == RV_GEN_MIX) {
+                    const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
+                    part[1] += 2.0 * static_cast<double>(mu) * mu * a;
+                } else {
+                    const float a = cgrad_stage<true>(f, lm, pk0, rows + (pa.lb - 1) * pa.rowcap, cd.cut_min, mu);
+                    part[1] += 2.0 * static_cast<double>(mu) * mu * a;
+                    const float2 tka = mix0[pa.la - 1];
+                    float wa = exp2f(pa.m0a * log2f(tka.y));
+                    const float ba = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, wa, pm);
+                    part[2] += 2.0 * static_cast<double>(ba);
+                    hxpose<GR, RL, RIO>(f, xb, tau);
+                    hxpose<GR, RL, RIO>(lm, xb, tau);
+                    store(f, pa.phi, item_off);
+                    store(lm, pa.lam, item_off);
+                }
             }
         }
     }
+    double* gp = pa.gpart + (static_cast<size_t>(bslot) * tiles + tile0) * (2 * p + 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (slot[i] >= 0) {
+            const double t = block_sum<H::W>(part[i], red);
+            if (tid == 0) gp[slot[i]] += t;
+        }
 }
 
 }  // namespace qaoa

@@ -345,6 +345,10 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
         if (need_lam && (st = grow(P->d_lam, P->cap_lam, static_cast<size_t>(B) << k, msg)) != QAOA_OK) return st;
         if ((st = grow(P->d_gpart, P->cap_gpart, static_cast<size_t>(B) * tiles * stride, msg)) != QAOA_OK) return st;
         const std::vector<PassSpec> prog = hbm_program(k, p, grad);
+        // tiles per workgroup: up to 8 while the class keeps >= 4096 workgroups (16 per CU);
+        // fixed per class, so an item's sums run in the same order whatever the batching
+        int tpw = 1;
+        while (tpw < 8 && 2 * tpw <= tiles && items * tiles / (2 * tpw) >= 4096) tpw *= 2;
         QCHECK(tm.begin(k, items));
         for (int64_t i0 = 0; i0 < items; i0 += B) {
             const int64_t nb = std::min<int64_t>(B, items - i0);
@@ -370,6 +374,7 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
                 pa.rowcap = grp.rowcap;
                 pa.fix_layer = ps.fix_layer;
                 pa.fix_pow = ps.fix_pow;
+                pa.tpw = tpw;
                 pa.ea = ea;
                 QCHECK(launch_pass(ps.kind, pa, stream));
             }
