@@ -51,8 +51,10 @@ def flops_fwd_adj(k: int, p: int) -> float:
     Adjoint: beta_p inner products (8), undo last mixer on two states (24), p gamma inner
     products (5), p-1 phases undone on two states (12), p-1 full layers undone on two
     states with their inner products (16k).
+    Per stored amplitude: cones of k >= 3 qubits keep only the half of the state with
+    qubit k-1 = 0 (the state is invariant under flipping every qubit), 2^(k-1) amplitudes.
     """
-    n = float(1 << k)
+    n = float(1 << (k - 1 if k >= 3 else k))
     fwd = 2 + (p - 1) * (6 * k + 6) + 12 + 4
     adj = 8 + 24 + 5 * p + 12 * (p - 1) + 16 * k * (p - 1)
     return n * (fwd + adj)

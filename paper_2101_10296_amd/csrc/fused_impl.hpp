@@ -21,6 +21,12 @@
 //   d zz / d beta_l  = 2 Im <lambda| sum_j X_j |psi>   (taken while undoing mixer l)
 //   d zz / d gamma_l = 2 Im <lambda| C |psi>          (after mixer l is undone)
 // The forward state is recovered by the inverse layers, not stored.
+//
+// Global-flip halving (K >= 3): |+>, C(x) and every mixer are invariant under flipping all
+// K qubits, so psi_x = psi_(x xor 1...1) and the same holds for lambda = Z_0 Z_1 psi.  Only
+// the half with qubit K-1 = 0 is kept (the layout above is applied to K-1 qubits); the
+// mixer of qubit K-1 pairs a stored amplitude with the complement of its index over the
+// stored bits, and every sum over the half is doubled.
 #pragma once
 
 #include "device.hpp"
@@ -177,6 +183,86 @@ __device__ __forceinline__ void xpose(float2 (&v)[A], float2* xb, uint32_t tau) 
 }
 
 
+// Global-flip halving.  Every cone state is invariant under flipping all K qubits, so only
+// the half with qubit K-1 = 0 is stored: amplitude y (K-1 bits) stands for both y and its
+// complement over all K bits.  The mixer of qubit K-1 then pairs y with ybar = y xor
+// (2^(K-1) - 1), the complement over the stored bits, which lives in thread ~tau, register
+// A-1-r of the same layout.  These transposes apply that butterfly on the way through LDS.
+template <int K, int G, int FROM, int TO, int A>
+__device__ __forceinline__ void xpose_flip(float2 (&v)[A], float2* xb, uint32_t tau, float t) {
+    constexpr uint32_t TM = Fz<K, G>::TPI - 1;
+    float2* pf = xb + opaque_u32(pad(tbase<K, G, FROM>(tau)));
+    const float2* pt = xb + opaque_u32(pad(tbase<K, G, TO>(tau)));
+    const float2* pc = xb + opaque_u32(pad(tbase<K, G, TO>(~tau & TM)));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 a = pt[pad(roff<K, G, TO>(r))];
+        const float2 b = pc[pad(roff<K, G, TO>(A - 1 - r))];
+        v[r] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Undo the flip-qubit butterfly on psi and lambda while transposing both.  Returns the
+// thread's share of Im <lambda| X_(K-1) |psi> on the values before the undo (the undone
+// pair differs from them by the factor 1/|kappa|^2, which the caller's weight accounts for).
+template <int K, int G, int FROM, int TO, int A>
+__device__ __forceinline__ float xpose2_unflip(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t) {
+    constexpr uint32_t TM = Fz<K, G>::TPI - 1;
+    float2* pf = xb + opaque_u32(pad(tbase<K, G, FROM>(tau)));
+    const float2* pt = xb + opaque_u32(pad(tbase<K, G, TO>(tau)));
+    const float2* pc = xb + opaque_u32(pad(tbase<K, G, TO>(~tau & TM)));
+    float2 fp[A];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = f[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        f[r] = pt[pad(roff<K, G, TO>(r))];
+        fp[r] = pc[pad(roff<K, G, TO>(A - 1 - r))];
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = l[r];
+    __syncthreads();
+    float acc = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 lo = pt[pad(roff<K, G, TO>(r))];
+        const float2 lq = pc[pad(roff<K, G, TO>(A - 1 - r))];
+        cacc(acc, 1.f, lo, fp[r]);
+        l[r] = make_float2(fmaf(-t, lq.y, lo.x), fmaf(t, lq.x, lo.y));
+        f[r] = make_float2(fmaf(-t, fp[r].y, f[r].x), fmaf(t, fp[r].x, f[r].y));
+        if ((r & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// The same with the whole item in one thread's registers (complement partner A-1-r).
+template <int A>
+__device__ __forceinline__ void reg_flip(float2 (&v)[A], float t) {
+#pragma unroll
+    for (int r = 0; r < A / 2; ++r) bfly(v[r], v[A - 1 - r], t);
+}
+template <int A>
+__device__ __forceinline__ float reg_unflip2(float2 (&f)[A], float2 (&l)[A], float t) {
+    float acc = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) cacc(acc, 1.f, l[r], f[A - 1 - r]);
+#pragma unroll
+    for (int r = 0; r < A / 2; ++r) {
+        bfly(f[r], f[A - 1 - r], -t);
+        bfly(l[r], l[A - 1 - r], -t);
+    }
+    return acc;
+}
+
 // Cut values of the thread's amplitudes in stage ST, packed four bytes per register.
 template <int K, int G, int ST, int A>
 __device__ __forceinline__ void load_cuts(uint32_t (&pk)[(A + 3) / 4], const uint8_t* cut, uint32_t tau) {
@@ -258,7 +344,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 // One full mixer layer on a state that sits in the layer's first stage.  Ascending
 // layers visit stages 0..S-1, descending ones S-1..0; a layer ends in the stage where
 // the next one (of the opposite direction) starts.
-template <int K, int G, bool DESC, int A>
+// With FLIP the layout holds K stored qubits of a (K+1)-qubit cone and the mixer of the
+// dropped qubit rides on the layer's first transpose (or on the registers if there is none).
+template <int K, int G, bool DESC, bool FLIP, int A>
 __device__ __forceinline__ void fwd_layer(float2 (&f)[A], float2* xb, uint32_t tau, float t) {
     constexpr int S = Fz<K, G>::S;
     static_for<0, S>([&](auto J) {
@@ -266,27 +354,38 @@ __device__ __forceinline__ void fwd_layer(float2 (&f)[A], float2* xb, uint32_t t
         constexpr int st = DESC ? S - 1 - j : j;
         if constexpr (j > 0) {
             constexpr int prev = DESC ? S - j : j - 1;
-            xpose<K, G, prev, st>(f, xb, tau);
+            if constexpr (FLIP && j == 1) xpose_flip<K, G, prev, st>(f, xb, tau, t);
+            else xpose<K, G, prev, st>(f, xb, tau);
         }
         mix_stage<K, G, st>(f, t);
     });
+    if constexpr (FLIP && S == 1) reg_flip(f, t);
 }
 
 // Undo a forward layer of direction DESC on psi and lambda (stages in reverse order);
 // returns the thread's share of Im <lambda| sum_j X_j |psi>.
-template <int K, int G, bool DESC, int A>
+template <int K, int G, bool DESC, bool FLIP, int A>
 __device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t,
                                           float k2) {
     constexpr int S = Fz<K, G>::S;
     double acc = 0.0;
     float w = 1.f;
+    if constexpr (FLIP && S == 1) {
+        acc += static_cast<double>(w * reg_unflip2(f, l, t));
+        w *= k2;
+    }
     static_for<0, S>([&](auto J) {
         constexpr int j = decltype(J)::value;            // j-th stage of the reverse walk
         constexpr int st = DESC ? j : S - 1 - j;
         if constexpr (j > 0) {
             constexpr int prev = DESC ? j - 1 : S - j;
-            xpose<K, G, prev, st>(f, xb, tau);
-            xpose<K, G, prev, st>(l, xb, tau);
+            if constexpr (FLIP && j == 1) {
+                acc += static_cast<double>(w * xpose2_unflip<K, G, prev, st>(f, l, xb, tau, t));
+                w *= k2;
+            } else {
+                xpose<K, G, prev, st>(f, xb, tau);
+                xpose<K, G, prev, st>(l, xb, tau);
+            }
         }
         acc += static_cast<double>(unmix_stage2<K, G, st>(f, l, t, k2, w));
     });
@@ -320,11 +419,16 @@ __device__ __forceinline__ double item_sum(double x, double* red, int tid) {
 // is peeled off; the remaining layers come in (ascending, descending) pairs, so no branch
 // ever selects between the two layer bodies.
 template <int K, bool GRAD, bool ODD>
-__global__ void __launch_bounds__((Fz<K, (GRAD ? 1 : 0)>::WG))
+__global__ void __launch_bounds__((Fz<(K >= 3 ? K - 1 : K), (GRAD ? 1 : 0)>::WG))
 k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         const uint8_t* __restrict__ cut_tables, int32_t rowcap, EvalArgs ea) {
     constexpr int GI = GRAD ? 1 : 0;
-    using C = Fz<K, GI>;
+    // FLIP: the state is stored on KL = K - 1 qubits (global-flip halving); every sum over
+    // the stored half is half the sum over the whole state
+    constexpr bool FLIP = K >= 3;
+    constexpr int KL = FLIP ? K - 1 : K;
+    constexpr double HS = FLIP ? 2.0 : 1.0;
+    using C = Fz<KL, GI>;
     constexpr int A = C::A;
     __shared__ float2 xbuf[C::S > 1 ? C::IPW * C::NPAD : 1];
     __shared__ __attribute__((aligned(16))) uint8_t cutl[C::IPW * C::N < 16 ? 16 : C::IPW * C::N];
@@ -370,8 +474,8 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     constexpr int NW = (A + 3) / 4;
     __syncthreads();
     uint32_t pk0[NW], pkL[NW];
-    load_cuts<K, GI, 0, A>(pk0, cut, tau);
-    load_cuts<K, GI, SL, A>(pkL, cut, tau);
+    load_cuts<KL, GI, 0, A>(pk0, cut, tau);
+    load_cuts<KL, GI, SL, A>(pkL, cut, tau);
     // mix0[l] = (tau_l, |kappa_l|^2); a full factored layer scales the state by
     // 1/|kappa|^K, the truncated last layer (qubits 0, 1) by 1/|kappa_p|^2.
     auto kpowK = [&](float k2) { return exp2f(0.5f * K * log2f(k2)); };
@@ -389,16 +493,16 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     int l1 = 1;
     if constexpr (ODD) {
         const float2 tk = mix0[0];
-        fwd_layer<K, GI, true>(f, xb, tau, tk.x);
+        fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tk.x);
         phase_stage(f, pk0, ROW(1), kpowK(tk.y) * (p == 2 ? k2p : 1.f));
         l1 = 2;
     }
     for (; l1 + 1 <= p - 1; l1 += 2) {
         const float2 ta = mix0[l1 - 1];
-        fwd_layer<K, GI, false>(f, xb, tau, ta.x);
+        fwd_layer<KL, GI, false, FLIP>(f, xb, tau, ta.x);
         phase_stage(f, pkL, ROW(l1), kpowK(ta.y));
         const float2 tb = mix0[l1];
-        fwd_layer<K, GI, true>(f, xb, tau, tb.x);
+        fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tb.x);
         phase_stage(f, pk0, ROW(l1 + 1), kpowK(tb.y) * (l1 + 2 == p ? k2p : 1.f));
     }
 
@@ -416,7 +520,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         const double pr = static_cast<double>(fmaf(f[r].x, f[r].x, f[r].y * f[r].y));
         zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
     }
-    const double zz = item_sum<K, GI>(zzp, red, tid);
+    const double zz = item_sum<KL, GI>(HS * zzp, red, tid);
     if (valid && tau == 0) ea.zz[static_cast<size_t>(point) * ea.M + cd.orbit] = zz;
 
     if constexpr (GRAD) {
@@ -433,7 +537,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
 #pragma unroll
         for (int r = 0; r < A; ++r)
             if (!(r & 2)) xacc(acc, lam[r], lam[r | 2], f[r], f[r | 2]);
-        const double gbp = item_sum<K, GI>(2.0 * static_cast<double>(acc), red, tid);
+        const double gbp = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(acc), red, tid);
         if (valid && tau == 0) gout[static_cast<size_t>(2 * p - 1) * M] = gbp;
         // undo the last mixer: both states end up scaled by 1/|kappa_p|^2
 #pragma unroll
@@ -452,38 +556,38 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         for (;;) {
             if (ly == 1) {
                 const float a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
-                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[0] = gc;
                 break;
             }
             {
                 const float a = cgrad_stage<true>(f, lam, pk0, ROW(ly - 1), cd.cut_min, mu);
-                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
             }
             {
                 const float2 tk = mix0[ly - 2];
-                const double b = unlayer<K, GI, true>(f, lam, xb, tau, tk.x, tk.y);
-                const double gb = item_sum<K, GI>(2.0 * b, red, tid);
+                const double b = unlayer<KL, GI, true, FLIP>(f, lam, xb, tau, tk.x, tk.y);
+                const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
                 mu = kpowK(tk.y);
             }
             --ly;
             if (ly == 1) {
                 const float a = cgrad_stage<false>(f, lam, pkL, ROW(0), cd.cut_min, 1.f);
-                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[0] = gc;
                 break;
             }
             {
                 const float a = cgrad_stage<true>(f, lam, pkL, ROW(ly - 1), cd.cut_min, mu);
-                const double gc = item_sum<K, GI>(2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
             }
             {
                 const float2 tk = mix0[ly - 2];
-                const double b = unlayer<K, GI, false>(f, lam, xb, tau, tk.x, tk.y);
-                const double gb = item_sum<K, GI>(2.0 * b, red, tid);
+                const double b = unlayer<KL, GI, false, FLIP>(f, lam, xb, tau, tk.x, tk.y);
+                const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
                 mu = kpowK(tk.y);
             }
@@ -496,8 +600,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
 template <int K>
 hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
                            const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
-    const int ipw = grad ? Fz<K, 1>::IPW : Fz<K, 0>::IPW;
-    const int wg = grad ? Fz<K, 1>::WG : Fz<K, 0>::WG;
+    constexpr int KL = K >= 3 ? K - 1 : K;   // stored qubits (global-flip halving)
+    const int ipw = grad ? Fz<KL, 1>::IPW : Fz<KL, 0>::IPW;
+    const int wg = grad ? Fz<KL, 1>::WG : Fz<KL, 0>::WG;
     const int64_t todo = n_items - item_base;
     const int64_t blocks = (todo + ipw - 1) / ipw;
     if (blocks <= 0) return hipSuccess;
