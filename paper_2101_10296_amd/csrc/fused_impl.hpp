@@ -36,9 +36,12 @@
 namespace qaoa {
 
 // G = 1 for the adjoint kernels, which hold two states and use 16 amplitudes per thread.
+#ifndef QAOA_FUSED_AB_GRAD
+#define QAOA_FUSED_AB_GRAD 4
+#endif
 template <int K, int G = 0>
 struct Fz {
-    static constexpr int AB_MAX = G ? 4 : 5;
+    static constexpr int AB_MAX = G ? QAOA_FUSED_AB_GRAD : 5;
     static constexpr int AB = K < AB_MAX ? K : AB_MAX;  // register bits
     static constexpr int A = 1 << AB;              // amplitudes per thread per state
     static constexpr int TB = K - AB;              // thread bits per item

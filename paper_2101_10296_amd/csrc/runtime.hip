@@ -29,6 +29,7 @@ qaoa_status grow(T*& ptr, size_t& cap, size_t need, std::string& msg) {
     const size_t bytes = std::max<size_t>(need, 1) * sizeof(T);
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), bytes);
     if (e != hipSuccess) {
+        (void)hipGetLastError();   // clear the failure so later launch checks do not see it
         ptr = nullptr;
         msg = "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
         return QAOA_ENOMEM;
@@ -341,9 +342,22 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
             return QAOA_ENOMEM;
         }
         B = std::min<int64_t>(B, items);
-        if (need_phi && (st = grow(P->d_phi, P->cap_phi, static_cast<size_t>(B) << k, msg)) != QAOA_OK) return st;
-        if (need_lam && (st = grow(P->d_lam, P->cap_lam, static_cast<size_t>(B) << k, msg)) != QAOA_OK) return st;
-        if ((st = grow(P->d_gpart, P->cap_gpart, static_cast<size_t>(B) * tiles * stride, msg)) != QAOA_OK) return st;
+        // free memory can be fragmented or held by other allocators: on a failed allocation
+        // the batch is halved until one item does not fit either
+        for (;;) {
+            st = QAOA_OK;
+            if (need_phi) st = grow(P->d_phi, P->cap_phi, static_cast<size_t>(B) << k, msg);
+            if (st == QAOA_OK && need_lam) st = grow(P->d_lam, P->cap_lam, static_cast<size_t>(B) << k, msg);
+            if (st == QAOA_OK) st = grow(P->d_gpart, P->cap_gpart, static_cast<size_t>(B) * tiles * stride, msg);
+            if (st != QAOA_ENOMEM || B == 1) break;
+            for (float2** b : {&P->d_phi, &P->d_lam}) {
+                hipFree(*b);
+                *b = nullptr;
+            }
+            P->cap_phi = P->cap_lam = 0;
+            B /= 2;
+        }
+        if (st != QAOA_OK) return st;
         const std::vector<PassSpec> prog = hbm_program(k, p, grad);
         // tiles per workgroup: up to 8 while the class keeps >= 4096 workgroups (16 per CU);
         // fixed per class, so an item's sums run in the same order whatever the batching
