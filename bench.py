@@ -33,13 +33,27 @@ HBM_TRAFFIC = {"sources_sha256": "00b8793e1c7e74ebeba704e9e22c88fc850ae3cfb19ee9
                "counted_over_algorithmic": 1.006}
 
 
-def hbm_sources_sha256() -> str:
+# Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
+# item (cut tables and phase rows read, five FP64 results written).
+FUSED_TRAFFIC = {"sources_sha256": "3a0b10049d47de96ccd334f3a9dc07559c2a32aae9784c22eceb1079f5ec1c8e",
+                 "bytes_per_item": 297.5}
+
+
+def sources_sha256(files) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_2101_10296_amd/csrc/hbm_impl.hpp", "paper_2101_10296_amd/csrc/hbm.hip"):
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def hbm_sources_sha256() -> str:
+    return sources_sha256(("paper_2101_10296_amd/csrc/hbm_impl.hpp", "paper_2101_10296_amd/csrc/hbm.hip"))
+
+
+def fused_sources_sha256() -> str:
+    return sources_sha256(("paper_2101_10296_amd/csrc/fused_impl.hpp", "paper_2101_10296_amd/csrc/fused_k14.hip"))
 
 
 def flops_fwd_adj(k: int, p: int) -> float:
@@ -253,8 +267,11 @@ def main():
                                                   key=lambda kv: kv[1][0])
     flop = flops_fwd_adj(kdom, pdom) * items_dom
     achieved = flop / (ms_dom * 1e-3) / 1e12
+    traffic = None   # counted HBM bytes per launch, if the counters are current for this kernel
+    if kdom == 14 and fused_sources_sha256() == FUSED_TRAFFIC["sources_sha256"]:
+        traffic = round(FUSED_TRAFFIC["bytes_per_item"] * items_dom / a.steps)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": f"k_fused<K={kdom},grad>", "avg_launch_ms": round(ms_dom / a.steps, 4),
                 "items_per_launch": items_dom // a.steps}
 
@@ -309,6 +326,8 @@ def main():
     line.update(extra)
     if a.hbm_points > 0:
         line["hbm"] = hbm_measure(Q, torch, W, a.hbm_points)
+    if a.copy_gib > 0:
+        line["copy"] = copy_measure(torch, a.copy_gib)
     if not a.no_cpu_baseline:
         v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
         line["cpu_baseline"] = {"value": round(v, 6), "unit": "evals/s", "cores": 1, "kind": "oracle",
