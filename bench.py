@@ -180,6 +180,31 @@ def hbm_measure(Q, torch, W, points: int) -> dict:
             "achieved_GBps_by_k": by_k}
 
 
+def replay_measure(Q, torch, W, calls: int = 200) -> dict:
+    """Per-call time of a small training-loop evaluation (energy and gradient of C_10000(1,2)
+    reduced to its two orbits, p=2, one angle point), eager launches against graph replay."""
+    out = {}
+    for name, g, p in (("C10000(1,2) p=2", W.circulant(10000, (1, 2)), 2),):
+        ga, be = W.draw_angles(1, p, 77)
+        gt = torch.tensor(ga, dtype=torch.float64, device="cuda")
+        bt = torch.tensor(be, dtype=torch.float64, device="cuda")
+        res = {}
+        for mode in (False, True):
+            pl = Q.Plan(g.n, g.edges, p=p, generators=g.gens(), graph=mode)
+            o = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty_like(gt), torch.empty_like(bt))
+            for _ in range(3):
+                pl.energy_grad(gt, bt, out=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                pl.energy_grad(gt, bt, out=o)
+            torch.cuda.synchronize()
+            res["replay_us" if mode else "eager_us"] = round((time.perf_counter() - t0) / calls * 1e6, 1)
+            pl.close()
+        out[name] = res
+    return out
+
+
 def copy_measure(torch, gib: float) -> dict:
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     n = int(gib * (1 << 30)) // 4
@@ -312,6 +337,7 @@ def main():
         extra["symmetry_speedup_circulant"] = round(ts[1] / ts[0], 1)
         red.close()
         unr.close()
+        extra["graph_replay"] = replay_measure(Q, torch, W)
 
     line = {
         "metric": "QAOA energy+grad evals/s (batched adjoint vs plain); achieved HBM GB/s",

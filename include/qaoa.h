@@ -86,6 +86,12 @@ typedef struct {
     int32_t one_cone_at_a_time;   /* 1 = plain GPU path: one launch per (cone, point) */
     int32_t profile;              /* 1 = record HIP events around every kernel group of each
                                      energy call (read with qaoa_plan_kernel_times) */
+    int32_t graph;                /* 1 = replay: the first call with a given (n_points, gradient
+                                     or not, device pointers) runs eagerly and captures its launch
+                                     sequence into a HIP graph; later calls with the same key
+                                     replay the graph on the caller's stream (angle values may
+                                     change in place between calls).  Not with profile or
+                                     one_cone_at_a_time. */
 } qaoa_plan_opts;
 
 typedef struct {
@@ -99,6 +105,7 @@ typedef struct {
     int32_t cut_min, cut_max;     /* range of cut values over all cones */
     int64_t n_hbm_cones;          /* cones too large for one workgroup (state kept in HBM) */
     int64_t device_bytes;         /* descriptor and table bytes resident on the device */
+    int64_t graph_replays;        /* energy calls served by replaying a captured graph */
 } qaoa_plan_info;
 
 void qaoa_plan_opts_default(qaoa_plan_opts* opts);

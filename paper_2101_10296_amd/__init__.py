@@ -46,7 +46,8 @@ class Plan:
 
     def __init__(self, n_nodes: int, edges, p: int, weights=None, generators=None, *, reduce: bool = True,
                  max_cone_qubits: int = 30, k_lds_max: int = 14, mem_budget_bytes: int = 0,
-                 checkpoint_mode: int = 0, one_cone_at_a_time: bool = False, profile: bool = False):
+                 checkpoint_mode: int = 0, one_cone_at_a_time: bool = False, profile: bool = False,
+                 graph: bool = False):
         L = _capi.lib()
         e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
         self._u = _i32(e[:, 0])
@@ -72,6 +73,7 @@ class Plan:
         o.checkpoint_mode = int(checkpoint_mode)
         o.one_cone_at_a_time = int(bool(one_cone_at_a_time))
         o.profile = int(bool(profile))
+        o.graph = int(bool(graph))
         h = C.c_void_p()
         _check(L.qaoa_plan_lightcones(C.byref(pr), C.byref(o), C.byref(h)))
         self._h = h
@@ -134,26 +136,42 @@ class Plan:
             raise ValueError("gamma and beta must have the same shape [P, p]")
         return g, b
 
-    def energy(self, gamma, beta, term_zz: bool = False):
-        """E [P] (and per-orbit <ZZ> [P, M] if term_zz) as cuda float64 tensors."""
+    @staticmethod
+    def _out(t, shape, device):
         import torch
+        if t is None:
+            return torch.empty(shape, dtype=torch.float64, device=device)
+        if tuple(t.shape) != tuple(shape) or t.dtype != torch.float64 or not t.is_contiguous() or t.device != device:
+            raise ValueError(f"output tensor must be contiguous float64 {tuple(shape)} on {device}")
+        return t
+
+    def energy(self, gamma, beta, term_zz: bool = False, out=None):
+        """E [P] (and per-orbit <ZZ> [P, M] if term_zz) as cuda float64 tensors.
+
+        out: optional preallocated E (or (E, zz) with term_zz), e.g. to keep device pointers
+        fixed for graph replay."""
         g, b = self._angles(gamma, beta)
         P = g.shape[0]
-        E = torch.empty(P, dtype=torch.float64, device=g.device)
-        zz = torch.empty((P, max(self.n_orbits, 1)), dtype=torch.float64, device=g.device) if term_zz else None
+        o = out if isinstance(out, (tuple, list)) else (out, None)
+        E = self._out(o[0], (P,), g.device)
+        zz = self._out(o[1], (P, max(self.n_orbits, 1)), g.device) if term_zz else None
+        import torch
         stream = torch.cuda.current_stream(g.device).cuda_stream
         _check(_capi.lib().qaoa_energy(self._h, P, g.data_ptr(), b.data_ptr(), E.data_ptr(),
                                        None if zz is None else zz.data_ptr(), stream))
         return (E, zz[:, : self.n_orbits]) if term_zz else E
 
-    def energy_grad(self, gamma, beta):
-        """(E [P], dE/dgamma [P, p], dE/dbeta [P, p]) as cuda float64 tensors."""
+    def energy_grad(self, gamma, beta, out=None):
+        """(E [P], dE/dgamma [P, p], dE/dbeta [P, p]) as cuda float64 tensors.
+
+        out: optional preallocated (E, dgamma, dbeta)."""
         import torch
         g, b = self._angles(gamma, beta)
         P = g.shape[0]
-        E = torch.empty(P, dtype=torch.float64, device=g.device)
-        dg = torch.empty_like(g)
-        db = torch.empty_like(b)
+        o = out if out is not None else (None, None, None)
+        E = self._out(o[0], (P,), g.device)
+        dg = self._out(o[1], (P, self.p), g.device)
+        db = self._out(o[2], (P, self.p), g.device)
         stream = torch.cuda.current_stream(g.device).cuda_stream
         _check(_capi.lib().qaoa_energy_grad(self._h, P, g.data_ptr(), b.data_ptr(), E.data_ptr(),
                                             dg.data_ptr(), db.data_ptr(), stream))

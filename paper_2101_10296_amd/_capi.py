@@ -22,14 +22,15 @@ class Problem(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("reduce", C.c_int32), ("max_cone_qubits", C.c_int32),
                 ("k_lds_max", C.c_int32), ("checkpoint_mode", C.c_int32), ("one_cone_at_a_time", C.c_int32),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("graph", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("p", C.c_int32), ("n_edges", C.c_int64), ("n_orbits", C.c_int64),
                 ("min_k", C.c_int32), ("max_k", C.c_int32), ("k_hist", C.c_int64 * 31),
                 ("total_weight", C.c_double), ("cut_min", C.c_int32), ("cut_max", C.c_int32),
-                ("n_hbm_cones", C.c_int64), ("device_bytes", C.c_int64)]
+                ("n_hbm_cones", C.c_int64), ("device_bytes", C.c_int64),
+                ("graph_replays", C.c_int64)]
 
 
 _lib = None

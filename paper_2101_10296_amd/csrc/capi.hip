@@ -44,8 +44,12 @@ qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* o
         o.checkpoint_mode = opts->checkpoint_mode;
         o.one_cone_at_a_time = opts->one_cone_at_a_time;
         o.profile = opts->profile;
+        o.graph = opts->graph;
         if (o.mem_budget_bytes < 0) return set_err(QAOA_EINVAL, "mem_budget_bytes must be >= 0");
         if (o.reduce != 0 && o.reduce != 1) return set_err(QAOA_EINVAL, "reduce must be 0 or 1");
+        if (o.graph != 0 && o.graph != 1) return set_err(QAOA_EINVAL, "graph must be 0 or 1");
+        if (o.graph && (o.profile || o.one_cone_at_a_time))
+            return set_err(QAOA_EINVAL, "graph replay cannot be combined with profile or one_cone_at_a_time");
         if (o.checkpoint_mode != 0)
             return set_err(QAOA_EINVAL, "checkpoint_mode must be 0: the adjoint recovers forward states by inverse "
                                         "layers; stored per-pass states are not provided");
@@ -89,6 +93,7 @@ qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
     out->cut_min = hp.cut_min;
     out->cut_max = hp.cut_max;
     out->device_bytes = static_cast<int64_t>(plan->resident_bytes);
+    out->graph_replays = plan->graph_replays;
     return QAOA_OK;
 }
 

@@ -44,6 +44,7 @@ struct PlanOptions {
     int32_t checkpoint_mode = 0;
     int32_t one_cone_at_a_time = 0;
     int32_t profile = 0;
+    int32_t graph = 0;
 };
 
 // Throws PlanError on invalid input.

@@ -277,8 +277,13 @@ qaoa_status kernel_times(qaoa_plan_s* P, int32_t cap, int32_t* k_out, int64_t* i
     return QAOA_OK;
 }
 
-qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, const double* beta, double* energy,
-                       double* term_zz, double* dgamma, double* dbeta, hipStream_t stream, std::string& msg) {
+namespace {
+
+// The launch sequence of one energy call.  With fixed_batches the HBM groups reuse the
+// batch sizes of the previous call (and so allocate nothing): used while capturing.
+qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const double* beta, double* energy,
+                    double* term_zz, double* dgamma, double* dbeta, hipStream_t stream, bool fixed_batches,
+                    std::string& msg) {
     qaoa_status st = ensure_device(P, msg);
     if (st != QAOA_OK) return st;
     const HostPlan& hp = P->hp;
@@ -317,7 +322,9 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
         QCHECK(tm.end());
     }
     // ---- HBM-resident cones: batches of items through the pass program
-    for (const auto& grp : P->hbm_groups) {
+    if (!fixed_batches) P->hbm_batch.assign(P->hbm_groups.size(), 0);
+    for (size_t gi = 0; gi < P->hbm_groups.size(); ++gi) {
+        const auto& grp = P->hbm_groups[gi];
         const int k = grp.K;
         const int64_t items = grp.count * n_points;
         const int64_t tiles = int64_t{1} << (k - HT);
@@ -329,7 +336,9 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
         const size_t per_item = (need_phi ? state_bytes : 0) + (need_lam ? state_bytes : 0) +
                                 static_cast<size_t>(tiles) * stride * sizeof(double);
         size_t budget = static_cast<size_t>(P->opt.mem_budget_bytes);
-        if (budget == 0) {
+        if (fixed_batches) {
+            budget = per_item * static_cast<size_t>(P->hbm_batch[gi]);
+        } else if (budget == 0) {
             size_t fr = 0, tot = 0;
             QCHECK(hipMemGetInfo(&fr, &tot));
             const size_t held = P->cap_phi * sizeof(float2) + P->cap_lam * sizeof(float2) + P->cap_gpart * sizeof(double);
@@ -358,6 +367,7 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
             B /= 2;
         }
         if (st != QAOA_OK) return st;
+        P->hbm_batch[gi] = B;
         const std::vector<PassSpec> prog = hbm_program(k, p, grad);
         // tiles per workgroup: up to 8 while the class keeps >= 4096 workgroups (16 per CU);
         // fixed per class, so an item's sums run in the same order whatever the batching
@@ -402,7 +412,61 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
     return QAOA_OK;
 }
 
+void drop_graph(qaoa_plan_s* P) {
+    if (P->gexec) hipGraphExecDestroy(P->gexec);
+    P->gexec = nullptr;
+    P->gkey = qaoa_plan_s::GraphKey{};
+}
+
+}  // namespace
+
+qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, const double* beta, double* energy,
+                       double* term_zz, double* dgamma, double* dbeta, hipStream_t stream, std::string& msg) {
+    if (!P->opt.graph)
+        return enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, stream, false, msg);
+    qaoa_plan_s::GraphKey key;
+    key.n_points = n_points;
+    key.grad = dgamma != nullptr;
+    const void* ptrs[6] = {gamma, beta, energy, term_zz, dgamma, dbeta};
+    for (int i = 0; i < 6; ++i) key.ptr[i] = ptrs[i];
+    if (P->gexec && key == P->gkey) {
+        QCHECK(hipGraphLaunch(P->gexec, stream));
+        ++P->graph_replays;
+        return QAOA_OK;
+    }
+    // a new key: run eagerly (allocating what the call needs), then capture the same launch
+    // sequence on the plan's own stream; the graph is replayed from the next call on
+    drop_graph(P);
+    qaoa_status st = enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, stream, false, msg);
+    if (st != QAOA_OK) return st;
+    if (!P->cap_stream) QCHECK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    QCHECK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, P->cap_stream, true, msg);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(P->cap_stream, &graph);
+    if (st == QAOA_OK && ec != hipSuccess) {
+        msg = std::string("hipStreamEndCapture: ") + hipGetErrorString(ec);
+        st = QAOA_EHIP;
+    }
+    if (st == QAOA_OK) {
+        const hipError_t ei = hipGraphInstantiate(&P->gexec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            msg = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+            P->gexec = nullptr;
+            st = QAOA_EHIP;
+        }
+    }
+    if (graph) hipGraphDestroy(graph);
+    if (st == QAOA_OK) P->gkey = key;
+    return st;
+}
+
 void release_device(qaoa_plan_s* P) {
+    drop_graph(P);
+    if (P->cap_stream) {
+        hipStreamDestroy(P->cap_stream);
+        P->cap_stream = nullptr;
+    }
     for (auto& t : P->timed) {
         hipEventDestroy(t.start);
         hipEventDestroy(t.stop);

@@ -60,6 +60,24 @@ struct qaoa_plan_s {
     float2* d_phi = nullptr;
     float2* d_lam = nullptr;
     double* d_gpart = nullptr;
+    std::vector<int64_t> hbm_batch;     // items per batch of each HBM group in the last call
+
+    // ---- graph replay (opts.graph)
+    struct GraphKey {
+        int64_t n_points = -1;
+        bool grad = false;
+        const void* ptr[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        bool operator==(const GraphKey& o) const {
+            if (n_points != o.n_points || grad != o.grad) return false;
+            for (int i = 0; i < 6; ++i)
+                if (ptr[i] != o.ptr[i]) return false;
+            return true;
+        }
+    };
+    GraphKey gkey;
+    hipGraphExec_t gexec = nullptr;
+    int64_t graph_replays = 0;
+    hipStream_t cap_stream = nullptr;
 };
 
 namespace qaoa {
