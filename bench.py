@@ -29,8 +29,8 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "00b8793e1c7e74ebeba704e9e22c88fc850ae3cfb19ee9269ea34cea98b54e8d",
-               "counted_over_algorithmic": 1.006}
+HBM_TRAFFIC = {"sources_sha256": "c036d4071bbd85c9c5ebc2352594c7aae1aceef5f182d07eee65474048fa443f",
+               "counted_over_algorithmic": 1.022}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
@@ -74,23 +74,25 @@ def flops_fwd_adj(k: int, p: int) -> float:
     return n * (fwd + adj)
 
 
-def hbm_groups(k: int) -> int:
-    """Pass groups of a k-qubit cone held in device memory: qubits 0..12, then nine at a time."""
-    return 1 + (k - 13 + 8) // 9
+def hbm_groups(kh: int) -> int:
+    """Pass groups over the kh stored qubits of a cone held in device memory: qubits 0..12,
+    then nine at a time."""
+    return 1 + (kh - 13 + 8) // 9
 
 
 def hbm_bytes_per_item(k: int, p: int, grad: bool) -> float:
     """Algorithmic HBM bytes of one (cone, point) item of the device-memory pass program.
 
-    8 B per complex64 amplitude read or written.  Forward: the first pass writes the state,
-    every later pass reads and writes it, the final pass only reads it (with the gradient it
-    also writes lambda).  Reverse: every pass but the last reads and writes psi and lambda;
-    the last (undoing the first forward pass) only reads them.  p = 1 keeps no state.
+    8 B per stored complex64 amplitude read or written; the stored half of the state has
+    2^(k-1) amplitudes (qubit k-1 = 0).  Forward: the first pass writes the state, every
+    later pass reads and writes it, the final pass only reads it (with the gradient it also
+    writes lambda).  Reverse: every pass but the last reads and writes psi and lambda; the
+    last (undoing the first forward pass) only reads them.  p = 1 keeps no state.
     """
     if p == 1:
         return 0.0
-    F = (p - 1) * (hbm_groups(k) - 1)   # passes after the first (k > 13: at least two groups)
-    n = float(1 << k)
+    F = (p - 1) * (hbm_groups(k - 1) - 1)   # passes after the first (at least two groups)
+    n = float(1 << (k - 1))
     if grad:
         return n * (8 + 16 * (F - 1) + 16 + 16 + 32 * (F - 1))
     return n * (8 + 16 * (F - 1) + 8)

@@ -79,7 +79,7 @@ typedef struct {
     int32_t max_cone_qubits;      /* 0 = 30 */
     int32_t k_lds_max;            /* cones with k <= this run entirely inside one workgroup,
                                      larger ones as passes over tiles held in device memory
-                                     (0 = default 14; 13 or 14) */
+                                     (0 = default; only 14 is accepted) */
     int32_t checkpoint_mode;      /* adjoint of cones held in HBM: must be 0 = uncompute (the
                                      forward state is recovered by inverse layers, two live
                                      states per item); any other value -> QAOA_EINVAL */

@@ -16,7 +16,7 @@ __global__ void k_tt_tables(const ConeHbm* __restrict__ cones, const int32_t* __
     __syncthreads();
     if (threadIdx.x < HT) {
         int h;
-        pos[hgroup_bits(cd.k, grp, threadIdx.x, h)] = threadIdx.x;
+        pos[hgroup_bits(cd.k - 1, grp, threadIdx.x, h)] = threadIdx.x;   // stored qubits
     }
     __syncthreads();
     uint8_t* out = tt + cones[blockIdx.x].tt_off[grp];
@@ -38,7 +38,8 @@ __global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
 }
 
 // Per item: fixed-order sum over tiles of the partial sums (stride values per tile);
-// j = 0 -> zz, j >= 1 -> d zz.
+// j = 0 -> zz, j >= 1 -> d zz.  The passes sum over the stored half of the state, so the
+// result is doubled.
 __global__ void __launch_bounds__(256)
 k_tile_reduce(const ConeHbm* __restrict__ cones, const double* __restrict__ gpart, int64_t item0, int64_t tiles,
               int32_t stride, EvalArgs ea) {
@@ -59,8 +60,8 @@ k_tile_reduce(const ConeHbm* __restrict__ cones, const double* __restrict__ gpar
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        if (j == 0) ea.zz[static_cast<size_t>(point) * ea.M + orbit] = sh[0];
-        else ea.g[(static_cast<size_t>(point) * 2 * ea.p + (j - 1)) * ea.M + orbit] = sh[0];
+        if (j == 0) ea.zz[static_cast<size_t>(point) * ea.M + orbit] = 2.0 * sh[0];
+        else ea.g[(static_cast<size_t>(point) * 2 * ea.p + (j - 1)) * ea.M + orbit] = 2.0 * sh[0];
     }
 }
 
@@ -68,12 +69,14 @@ k_tile_reduce(const ConeHbm* __restrict__ cones, const double* __restrict__ gpar
 // block reduction per workgroup); the caller picks tpw.
 template <int KIND, bool G0>
 static hipError_t launch_one(const PassArgs& pa, hipStream_t st) {
-    constexpr bool GR = KIND >= GR_GEN_FINAL;
-    const int64_t tiles = int64_t{1} << (pa.k - HT);
-    if (pa.tpw < 1 || tiles % pa.tpw != 0) return hipErrorInvalidValue;
-    const int64_t blocks = tiles * pa.n_batch / pa.tpw;
+    constexpr int CF = pass_cf(KIND, G0);
+    if (pa.kh != pa.k - 1 || pa.kh < HT + 1) return hipErrorInvalidValue;
+    const int64_t tiles = int64_t{1} << (pa.kh - HT);
+    const int64_t units = CF >= 2 ? tiles / 2 : tiles;   // tile pairs on group 0
+    if (pa.tpw < 1 || units % pa.tpw != 0) return hipErrorInvalidValue;
+    const int64_t blocks = units * pa.n_batch / pa.tpw;
     const size_t dyn = static_cast<size_t>(pa.ea.p) * pa.rowcap * sizeof(float2);
-    hipLaunchKernelGGL((k_pass<KIND, G0>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<GR>::W), dyn, st, pa);
+    hipLaunchKernelGGL((k_pass<KIND, G0>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<CF>::W), dyn, st, pa);
     return hipGetLastError();
 }
 

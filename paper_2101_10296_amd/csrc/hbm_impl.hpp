@@ -2,11 +2,18 @@
 // (cone, angle point) item lives in device memory and every layer is applied by passes
 // over tiles of 2^13 amplitudes.
 //
-// A pass works on one pass group of qubits.  Group 0 holds qubits 0..12 (so qubits 0 and
-// 1, u and v, for the final mixer and <Z0 Z1>); group j >= 1 holds up to nine of the
+// Global-flip halving: every cone state is invariant under flipping all k qubits, so only
+// the half with qubit k-1 = 0 is stored, on kh = k - 1 qubits; the mixer of qubit k-1
+// pairs stored index y with its complement over the kh stored bits.
+//
+// A pass works on one pass group of stored qubits.  Group 0 holds qubits 0..12 (so qubits
+// 0 and 1, u and v, for the final mixer and <Z0 Z1>); group j >= 1 holds up to nine of the
 // remaining qubits, 13 + 9(j-1) .. , and carries global bits 0..3 so that every row of a
 // tile is 16 contiguous amplitudes (128 bytes).  Tile bits map to global bits through
-// gmap; the bits outside the tile select the tile.
+// gmap; the bits outside the tile select the tile.  Passes of group 0 also apply the mixer
+// of qubit k-1: they take the tiles in complementary pairs (T, ~T) and hold tile ~T in
+// complemented coordinates (register r of thread tau stands for local index ~q(tau, r)),
+// so each amplitude's partner sits in the same register of the other tile.
 //
 // Layer order (the forward program, built on the host): layers alternate the order in
 // which they visit the groups, so that the last group of layer l is the first group of
@@ -23,6 +30,7 @@
 //   C(x) = C_oo(o) + sum_b W1_b(o) + sum_b q_b (WO_b - 2 W1_b(o)) + C_tt(q),
 // where b runs over tile bits, WO_b / W1_b are the weights of b's edges to outer bits
 // (all of them / those whose outer end is 1 in o), and C_tt is a per-(cone, group) table.
+// Qubit k-1 counts as an outer bit fixed at 0.
 #pragma once
 
 #include "fused_impl.hpp"
@@ -68,76 +76,76 @@ struct PassArgs {
     const int32_t* e_b;
     const int32_t* e_w;
     const uint8_t* tt;         // C_tt tables
-    float2* phi;               // state buffer [batch][2^k]
-    float2* lam;               // adjoint buffer [batch][2^k]
+    float2* phi;               // state buffer [batch][2^kh]
+    float2* lam;               // adjoint buffer [batch][2^kh]
     double* gpart;             // per (item, tile) partial sums [batch][tiles][2p + 1]
     int64_t item0;             // first item of the batch (item = slot * P + point)
     int32_t n_batch;           // items in the batch
     int32_t k;                 // cone qubits (same for every cone of the class)
+    int32_t kh;                // stored qubits, k - 1
     int32_t group;             // pass group
     int32_t la, lb;            // layers (1-based) of mixer A / phase + mixer B
     int32_t m0a, m0b;          // qubits of layers la / lb undone by earlier reverse passes
     int32_t rowcap;            // phase row capacity (largest cut range)
     int32_t fix_layer;         // > 0: the loaded psi is rescaled by |kappa_fix_layer|^fix_pow
     int32_t fix_pow;
-    int32_t tpw;               // tiles per workgroup (a power of two dividing the tile count)
+    int32_t tpw;               // tiles (pair passes: tile pairs) per workgroup, a power of two
     EvalArgs ea;
 };
 
-// Tuning (measured on MI355X over 20-30-qubit cones): register bits per thread and the
-// minimum waves per SIMD the compiler must allow.  Forward passes: 32 amplitudes per
-// thread, 256 threads; adjoint passes (two states): 16 per state, 512 threads, at most 128
-// registers so that two workgroups share a CU (LDS allows two).
-#ifndef QAOA_HBM_AB_FWD
-#define QAOA_HBM_AB_FWD 5
+// Register configurations (measured on MI355X over 20-30-qubit cones):
+//   CF 0  forward, one tile:        32 amplitudes per thread, 256 threads
+//   CF 1  adjoint (psi, lambda):    16 per state, 512 threads, <= 128 VGPRs (two per CU)
+//   CF 2  forward, tile pair:       16 per tile, 512 threads, <= 128 VGPRs
+//   CF 3  adjoint, tile pair:       16 per state and tile, 512 threads, one workgroup per CU
+//         (four states in registers; fewer amplitudes per thread spill at 1024 threads)
+#ifndef QAOA_HBM_CF3_AB
+#define QAOA_HBM_CF3_AB 4
 #endif
-#ifndef QAOA_HBM_AB_GR
-#define QAOA_HBM_AB_GR 4
+#ifndef QAOA_HBM_CF3_WPE
+#define QAOA_HBM_CF3_WPE 2
 #endif
-#ifndef QAOA_HBM_WPE_FWD
-#define QAOA_HBM_WPE_FWD 2
-#endif
-#ifndef QAOA_HBM_WPE_GR
-#define QAOA_HBM_WPE_GR 4
-#endif
-
-template <bool GR>
+template <int CF>
 struct Hz {
-    static constexpr int AB = GR ? QAOA_HBM_AB_GR : QAOA_HBM_AB_FWD;
+    static constexpr int AB = CF == 0 ? 5 : (CF == 3 ? QAOA_HBM_CF3_AB : 4);
     static constexpr int A = 1 << AB;
     static constexpr int W = 1 << (HT - AB);        // threads per tile
-    static constexpr int WPE = GR ? QAOA_HBM_WPE_GR : QAOA_HBM_WPE_FWD;   // minimum waves per SIMD
+    static constexpr int WPE = CF == 0 ? 2 : (CF == 3 ? QAOA_HBM_CF3_WPE : 4);   // minimum waves per SIMD
     static constexpr uint32_t NPAD = HN + (HN >> 5) + (HN >> 10);
     static constexpr int ROT_IO0 = HT - AB;          // I/O layout of group 0: lanes on tile bits 0..5
     static constexpr int ROT_IOJ = 9 - AB;           // I/O layout of groups >= 1: lanes on tile bits 9..12, 0, 1
 };
 
+__host__ __device__ constexpr int pass_cf(int kind, bool g0) {
+    return (kind >= GR_GEN_FINAL ? 1 : 0) + ((g0 && kind != FWD_GEN_FINAL && kind != GR_GEN_FINAL) ? 2 : 0);
+}
+
 __device__ constexpr uint32_t rotl13(uint32_t x, int s) {
     s %= HT;
     return s == 0 ? x : (((x << s) | (x >> (HT - s))) & (HN - 1u));
 }
-template <bool GR, int ROT>
+template <int CF, int ROT>
 __device__ constexpr uint32_t hroff(int r) { return rotl13(static_cast<uint32_t>(r), ROT); }
-template <bool GR, int ROT>
-__device__ __forceinline__ uint32_t htbase(uint32_t tau) { return rotl13(tau << Hz<GR>::AB, ROT); }
+template <int CF, int ROT>
+__device__ __forceinline__ uint32_t htbase(uint32_t tau) { return rotl13(tau << Hz<CF>::AB, ROT); }
 
-template <bool GR, int RF, int RT, int A>
+template <int CF, int RF, int RT, int A>
 __device__ __forceinline__ void hxpose(float2 (&v)[A], float2* xb, uint32_t tau) {
-    float2* pf = xb + opaque_u32(pad(htbase<GR, RF>(tau)));
-    const float2* pt = xb + opaque_u32(pad(htbase<GR, RT>(tau)));
+    float2* pf = xb + opaque_u32(pad(htbase<CF, RF>(tau)));
+    const float2* pt = xb + opaque_u32(pad(htbase<CF, RT>(tau)));
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) pf[pad(hroff<GR, RF>(r))] = v[r];
+    for (int r = 0; r < A; ++r) pf[pad(hroff<CF, RF>(r))] = v[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) v[r] = pt[pad(hroff<GR, RT>(r))];
+    for (int r = 0; r < A; ++r) v[r] = pt[pad(hroff<CF, RT>(r))];
 }
 
 // Mixer on the processed tile bits of layout ROT (tile bit b is processed when bit b of
 // pm is set; a butterfly with tau = 0 is the identity).  Wrapped bits belong to rotation 0.
-template <bool GR, int ROT, int A>
+template <int CF, int ROT, int A>
 __device__ __forceinline__ void hmix(float2 (&v)[A], float t, uint32_t pm) {
-    constexpr int AB = Hz<GR>::AB;
+    constexpr int AB = Hz<CF>::AB;
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
         if (ROT + i >= HT) continue;
@@ -155,9 +163,9 @@ __device__ __forceinline__ void hmix(float2 (&v)[A], float t, uint32_t pm) {
 
 // Undo the mixer on the processed bits of layout ROT for psi and lambda; returns the
 // weighted share of Im <lambda| sum_j X_j |psi> (see unmix_stage2).
-template <bool GR, int ROT, int A>
+template <int CF, int ROT, int A>
 __device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w, uint32_t pm) {
-    constexpr int AB = Hz<GR>::AB;
+    constexpr int AB = Hz<CF>::AB;
     float acc = 0.f;
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
@@ -186,48 +194,71 @@ __device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t
 
 // Processing layouts: rotations 0, AB, 2 AB, ...  Group 0 needs all 13 tile bits,
 // groups >= 1 at most 9 (tile bits 0..8).
-template <bool GR, bool G0>
+template <int CF, bool G0>
 struct HStages {
-    static constexpr int AB = Hz<GR>::AB;
+    static constexpr int AB = Hz<CF>::AB;
     static constexpr int NB = G0 ? HT : 9;
     static constexpr int S = (NB + AB - 1) / AB;
     static constexpr int rot(int s) { return s * AB; }
-    static constexpr int IO = G0 ? Hz<GR>::ROT_IO0 : Hz<GR>::ROT_IOJ;
+    static constexpr int IO = G0 ? Hz<CF>::ROT_IO0 : Hz<CF>::ROT_IOJ;
 };
 
 // Forward mixer over the group, visiting layouts S-1 .. 0 (DESC) or 0 .. S-1, starting in
 // layout FROM_ROT.  Ends in the last visited layout.
-template <bool GR, bool G0, bool DESC, int FROM_ROT, int A>
+template <int CF, bool G0, bool DESC, int FROM_ROT, int A>
 __device__ __forceinline__ void hmix_group(float2 (&f)[A], float2* xb, uint32_t tau, float t, uint32_t pm) {
-    using H = HStages<GR, G0>;
+    using H = HStages<CF, G0>;
     static_for<0, H::S>([&](auto J) {
         constexpr int j = decltype(J)::value;
         constexpr int st = DESC ? H::S - 1 - j : j;
         constexpr int prev = (j == 0) ? FROM_ROT : H::rot(DESC ? H::S - j : j - 1);
-        if constexpr (prev != H::rot(st)) hxpose<GR, prev, H::rot(st)>(f, xb, tau);
-        hmix<GR, H::rot(st)>(f, t, pm);
+        if constexpr (prev != H::rot(st)) hxpose<CF, prev, H::rot(st)>(f, xb, tau);
+        hmix<CF, H::rot(st)>(f, t, pm);
     });
 }
 
-template <bool GR, bool G0, bool DESC, int FROM_ROT, int A>
+template <int CF, bool G0, bool DESC, int FROM_ROT, int A>
 __device__ __forceinline__ float hunmix_group(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t,
                                               float k2, float& w, uint32_t pm) {
-    using H = HStages<GR, G0>;
+    using H = HStages<CF, G0>;
     float acc = 0.f;
     static_for<0, H::S>([&](auto J) {
         constexpr int j = decltype(J)::value;
         constexpr int st = DESC ? H::S - 1 - j : j;
         constexpr int prev = (j == 0) ? FROM_ROT : H::rot(DESC ? H::S - j : j - 1);
         if constexpr (prev != H::rot(st)) {
-            hxpose<GR, prev, H::rot(st)>(f, xb, tau);
-            hxpose<GR, prev, H::rot(st)>(l, xb, tau);
+            hxpose<CF, prev, H::rot(st)>(f, xb, tau);
+            hxpose<CF, prev, H::rot(st)>(l, xb, tau);
         }
-        acc += hunmix2<GR, H::rot(st)>(f, l, t, k2, w, pm);
+        acc += hunmix2<CF, H::rot(st)>(f, l, t, k2, w, pm);
     });
     return acc;
 }
 
-// Geometry of pass group grp for a k-qubit cone: tile bit i -> global bit gmap(i).
+// Mixer of the dropped qubit k-1 between the two tiles of a pair (partner in the same
+// register), and its undo on psi and lambda with the weighted share of Im <lambda|X|psi>.
+template <int A>
+__device__ __forceinline__ void hflip(float2 (&a)[A], float2 (&b)[A], float t) {
+#pragma unroll
+    for (int r = 0; r < A; ++r) bfly(a[r], b[r], t);
+}
+template <int A>
+__device__ __forceinline__ float hunflip2(float2 (&fa)[A], float2 (&fb)[A], float2 (&la)[A], float2 (&lb)[A], float t,
+                                          float k2, float& w) {
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        bfly(fa[r], fb[r], -t);
+        bfly(la[r], lb[r], -t);
+        if (r & 1) xacc(a1, la[r], lb[r], fa[r], fb[r]);
+        else xacc(a0, la[r], lb[r], fa[r], fb[r]);
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    w *= k2;
+    return w * (a0 + a1);
+}
+
+// Geometry of pass group grp over kh stored qubits: tile bit i -> global bit gmap(i).
 __device__ __forceinline__ int hgroup_bits(int k, int grp, int i, int& h) {
     if (grp == 0) {
         h = HT;
@@ -256,30 +287,34 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 }
 
 template <int KIND, bool G0>
-__global__ void __launch_bounds__((Hz<(KIND >= GR_GEN_FINAL)>::W), (Hz<(KIND >= GR_GEN_FINAL)>::WPE))
+__global__ void __launch_bounds__((Hz<pass_cf(KIND, G0)>::W), (Hz<pass_cf(KIND, G0)>::WPE))
 k_pass(PassArgs pa) {
+    constexpr int CF = pass_cf(KIND, G0);
     constexpr bool GR = KIND >= GR_GEN_FINAL;
-    using H = Hz<GR>;
-    using HS = HStages<GR, G0>;
+    constexpr bool PAIR = CF >= 2;
+    constexpr int NT = PAIR ? 2 : 1;                       // tiles held at once
+    using H = Hz<CF>;
+    using HS = HStages<CF, G0>;
     constexpr int A = H::A;
     constexpr int NW = (A + 3) / 4;
     constexpr bool FINAL = (KIND == FWD_GEN_FINAL || KIND == FWD_BND_FINAL || KIND == GR_GEN_FINAL ||
                             KIND == GR_BND_FINAL);
     __shared__ float2 xbuf[H::NPAD];
     __shared__ __attribute__((aligned(16))) uint8_t ttl[HN];
-    __shared__ int32_t lcoef[HT];
+    __shared__ int32_t lcoef[NT][HT];
     __shared__ double red[H::W / 64];
-    __shared__ int32_t k0_sh;
+    __shared__ int32_t k0_sh[NT];
     __shared__ int8_t tpos[32];          // tile bit of each global bit, -1 outside the tile
     extern __shared__ float2 rows[];   // [p][rowcap]
 
     const int tid = threadIdx.x;
     const uint32_t tau = static_cast<uint32_t>(tid);
-    const int k = pa.k;
-    const int64_t tiles = int64_t{1} << (k - HT);
-    const int64_t wpi = tiles / pa.tpw;                   // workgroups per item
+    const int k = pa.k, kh = pa.kh;
+    const int64_t tiles = int64_t{1} << (kh - HT);
+    const int64_t units = PAIR ? tiles / 2 : tiles;       // tiles or tile pairs per item
+    const int64_t wpi = units / pa.tpw;                   // workgroups per item
     const int64_t bslot = blockIdx.x / wpi;               // item within the batch
-    const int64_t tile0 = (blockIdx.x - bslot * wpi) * pa.tpw;
+    const int64_t unit0 = (blockIdx.x - bslot * wpi) * pa.tpw;
     const int64_t item = pa.item0 + bslot;
     const int P = pa.ea.P, p = pa.ea.p;
     const int64_t cslot = item / P;
@@ -289,7 +324,7 @@ k_pass(PassArgs pa) {
     // ---- per-item set-up: group geometry, C_tt table, phase rows
     int h = 0;
     uint32_t tmask = 0;  // global bits inside the tile
-    for (int i = 0; i < HT; ++i) tmask |= 1u << hgroup_bits(k, pa.group, i, h);
+    for (int i = 0; i < HT; ++i) tmask |= 1u << hgroup_bits(kh, pa.group, i, h);
     const uint32_t pm = (pa.group == 0) ? (HN - 1u) : ((1u << h) - 1u);
     const int32_t k0_base = pa.cones[cslot].tt_min[pa.group] - cd.cut_min;
     if (tid < 32) tpos[tid] = -1;
@@ -305,7 +340,7 @@ k_pass(PassArgs pa) {
     __syncthreads();
     if (tid < HT) {
         int hh;
-        tpos[hgroup_bits(k, pa.group, tid, hh)] = static_cast<int8_t>(tid);
+        tpos[hgroup_bits(kh, pa.group, tid, hh)] = static_cast<int8_t>(tid);
     }
     // the thread's first cone edge, kept in registers for every tile
     int e0a = 0, e0b = 0, e0w = 0;
@@ -316,43 +351,51 @@ k_pass(PassArgs pa) {
     }
 
     // ---- global addressing of the I/O layout.  The global bit of every tile bit depends
-    // only on (k, group), so the per-register offsets are uniform (scalar registers); only
+    // only on (kh, group), so the per-register offsets are uniform (scalar registers); only
     // the thread's own offset lives in a vector register.
     constexpr int RIO = HS::IO;
+    constexpr uint32_t TBITS_IO = rotl13(static_cast<uint32_t>(H::W - 1) << H::AB, RIO);  // thread bits
+    constexpr uint32_t TBITS_0 = static_cast<uint32_t>(H::W - 1) << H::AB;                // same, layout 0
     uint32_t gbit[HT];
 #pragma unroll
     for (int i = 0; i < HT; ++i) {
         int hh;
-        gbit[i] = static_cast<uint32_t>(hgroup_bits(k, pa.group, i, hh));
+        gbit[i] = static_cast<uint32_t>(hgroup_bits(kh, pa.group, i, hh));
     }
-    const uint32_t qio = htbase<GR, RIO>(tau);
-    // the thread's byte offset: its bits sit at most at global bit 26 (group 0: 12), so
-    // it fits 32 bits and the loads use a scalar base plus a 32-bit vector offset
-    uint32_t tbyte = 0;
+    const uint32_t qio = htbase<CF, RIO>(tau);
+    // the thread's byte offsets (its own tile coordinates, and complemented ones for the
+    // second tile of a pair): its bits sit at most at global bit 26 (group 0: 12), so they
+    // fit 32 bits and the loads use a scalar base plus a 32-bit vector offset
+    uint32_t tbyte = 0, tbyte_c = 0;
 #pragma unroll
-    for (int i = 0; i < HT; ++i)
+    for (int i = 0; i < HT; ++i) {
         if ((qio >> i) & 1u) tbyte += 8u << gbit[i];
+        if ((~qio & TBITS_IO) >> i & 1u) tbyte_c += 8u << gbit[i];
+    }
     auto io_off = [&](int r) -> uint64_t {
         uint64_t o = 0;
-        const uint32_t q = hroff<GR, RIO>(r);
+        const uint32_t q = hroff<CF, RIO>(r);
 #pragma unroll
         for (int i = 0; i < HT; ++i)
             if ((q >> i) & 1u) o += uint64_t{1} << gbit[i];
         return o;
     };
-    // (the thread offset is made opaque at every use so that no per-register address is
-    // computed ahead and held in vector registers)
-    auto load = [&](float2 (&v)[A], const float2* buf, size_t item_off) {
-        const uint32_t tb = opaque_u32(tbyte);
+    // tile t of the unit: t = 0 in its own coordinates, t = 1 (pairs) complemented: register
+    // r of thread tau holds local index ~q(tau, r) = (complemented thread bits) | roff(A-1-r).
+    // (The thread offset is made opaque at every use so that no per-register address is
+    // computed ahead and held in vector registers.)
+    auto load = [&](float2 (&v)[A], const float2* buf, size_t off, int t) {
+        const uint32_t tb = opaque_u32(t ? tbyte_c : tbyte);
 #pragma unroll
         for (int r = 0; r < A; ++r)
-            v[r] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(buf + item_off + io_off(r)) + tb);
+            v[r] = *reinterpret_cast<const float2*>(
+                reinterpret_cast<const char*>(buf + off + io_off(t ? A - 1 - r : r)) + tb);
     };
-    auto store = [&](const float2 (&v)[A], float2* buf, size_t item_off) {
-        const uint32_t tb = opaque_u32(tbyte);
+    auto store = [&](const float2 (&v)[A], float2* buf, size_t off, int t) {
+        const uint32_t tb = opaque_u32(t ? tbyte_c : tbyte);
 #pragma unroll
         for (int r = 0; r < A; ++r)
-            *reinterpret_cast<float2*>(reinterpret_cast<char*>(buf + item_off + io_off(r)) + tb) = v[r];
+            *reinterpret_cast<float2*>(reinterpret_cast<char*>(buf + off + io_off(t ? A - 1 - r : r)) + tb) = v[r];
     };
     float2* xb = xbuf;
     const float2* mix0 = pa.ea.mix + static_cast<size_t>(point) * p;
@@ -361,7 +404,7 @@ k_pass(PassArgs pa) {
     constexpr int RL = HS::rot(HS::S - 1);   // last processing layout
 
     // Per-thread partial sums over the workgroup's tiles, reduced once at the end into the
-    // slot of (item, first tile): [0] = zz, [1 + l - 1] = d/d gamma_l, [1 + p + l - 1] =
+    // slot of (item, first unit): [0] = zz, [1 + l - 1] = d/d gamma_l, [1 + p + l - 1] =
     // d/d beta_l.  Which partial goes to which slot depends on the pass kind.
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     int slot[4] = {-1, -1, -1, -1};
@@ -379,35 +422,47 @@ k_pass(PassArgs pa) {
         slot[0] = p + pa.lb; slot[1] = pa.lb; slot[2] = p + pa.la;
     }
 
-    for (int64_t tile = tile0; tile < tile0 + pa.tpw; ++tile) {
-        // ---- outer bits of this tile and its linear cut coefficients: an edge between tile
-        // bit b and an outer bit o adds w (1 - 2 x_o) to lcoef[b] and w x_o to k0; an edge
-        // between two outer bits adds w (x_o1 xor x_o2) to k0 (integer atomics: exact in
-        // any order)
-        uint64_t xo = 0;
-        {
+    for (int64_t unit = unit0; unit < unit0 + pa.tpw; ++unit) {
+        // ---- outer bits of the unit's tiles and their linear cut coefficients: an edge
+        // between tile bit b and an outer bit o adds w (1 - 2 x_o) to lcoef[b] and w x_o to
+        // k0; an edge between two outer bits adds w (x_o1 xor x_o2) to k0 (integer atomics:
+        // exact in any order).  Qubit k-1 is an outer bit fixed at 0.
+        uint64_t xo[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t tile = t ? tiles - 1 - unit : unit;
             int64_t o = tile;
-            for (int b = 0; b < k; ++b)
+            xo[t] = 0;
+            for (int b = 0; b < kh; ++b)
                 if (!((tmask >> b) & 1u)) {
-                    xo |= static_cast<uint64_t>(o & 1) << b;
+                    xo[t] |= static_cast<uint64_t>(o & 1) << b;
                     o >>= 1;
                 }
         }
-        __syncthreads();   // the previous tile has read lcoef and k0
-        if (tid < HT) lcoef[tid] = 0;
-        if (tid == 0) k0_sh = k0_base;
+        __syncthreads();   // the previous unit has read lcoef and k0
+        if (tid < HT) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) lcoef[t][tid] = 0;
+        }
+        if (tid == 0) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) k0_sh[t] = k0_base;
+        }
         __syncthreads();
         auto add_edge = [&](int a, int b, int w) {
             const int ia = tpos[a], ib = tpos[b];
-            const int xa = static_cast<int>((xo >> a) & 1u), xb2 = static_cast<int>((xo >> b) & 1u);
-            if (ia >= 0 && ib < 0) {
-                atomicAdd(&lcoef[ia], w - 2 * w * xb2);
-                if (xb2) atomicAdd(&k0_sh, w);
-            } else if (ia < 0 && ib >= 0) {
-                atomicAdd(&lcoef[ib], w - 2 * w * xa);
-                if (xa) atomicAdd(&k0_sh, w);
-            } else if (ia < 0 && ib < 0 && (xa ^ xb2)) {
-                atomicAdd(&k0_sh, w);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int xa = static_cast<int>((xo[t] >> a) & 1u), xb2 = static_cast<int>((xo[t] >> b) & 1u);
+                if (ia >= 0 && ib < 0) {
+                    atomicAdd(&lcoef[t][ia], w - 2 * w * xb2);
+                    if (xb2) atomicAdd(&k0_sh[t], w);
+                } else if (ia < 0 && ib >= 0) {
+                    atomicAdd(&lcoef[t][ib], w - 2 * w * xa);
+                    if (xa) atomicAdd(&k0_sh[t], w);
+                } else if (ia < 0 && ib < 0 && (xa ^ xb2)) {
+                    atomicAdd(&k0_sh[t], w);
+                }
             }
         };
         if (tid < cd.n_edges) add_edge(e0a, e0b, e0w);
@@ -416,155 +471,236 @@ k_pass(PassArgs pa) {
         __syncthreads();
 
         // packed cut values (minus cut_min) of the thread's amplitudes in layout rotation 0
-        uint32_t pk0[NW];
-        {
-            const uint32_t qb = htbase<GR, 0>(tau);
-            int32_t lthr = k0_sh;
+        uint32_t pk[NT][NW];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const uint32_t qb = t ? (~htbase<CF, 0>(tau) & TBITS_0) : htbase<CF, 0>(tau);
+            int32_t lthr = k0_sh[t];
 #pragma unroll
             for (int i = 0; i < HT; ++i)
-                if ((qb >> i) & 1u) lthr += lcoef[i];
+                if ((qb >> i) & 1u) lthr += lcoef[t][i];
 #pragma unroll
-            for (int w2 = 0; w2 < NW; ++w2) pk0[w2] = 0u;
+            for (int w2 = 0; w2 < NW; ++w2) pk[t][w2] = 0u;
 #pragma unroll
             for (int r = 0; r < A; ++r) {
-                int32_t c = lthr + ttl[qb | hroff<GR, 0>(r)];
+                const int rr = t ? A - 1 - r : r;
+                int32_t c = lthr + ttl[qb | hroff<CF, 0>(rr)];
 #pragma unroll
                 for (int i = 0; i < H::AB; ++i)
-                    if ((r >> i) & 1) c += lcoef[i];
-                pk0[r >> 2] |= static_cast<uint32_t>(c) << (8 * (r & 3));
+                    if ((rr >> i) & 1) c += lcoef[t][i];
+                pk[t][r >> 2] |= static_cast<uint32_t>(c) << (8 * (r & 3));
             }
         }
-        const size_t item_off = (static_cast<size_t>(bslot) << k) + xo;
+        size_t off[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) off[t] = (static_cast<size_t>(bslot) << kh) + xo[t];
 
-        float2 f[A];
+        float2 f[NT][A];
         // ------------------------------------------------------------ forward part
         if constexpr (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL) {
-            gen_stage(f, pk0, rows, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) gen_stage(f[t], pk[t], rows, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
             if constexpr (KIND == FWD_GEN_MIX) {
-                hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[0].x, pm);
-                hxpose<GR, RL, RIO>(f, xb, tau);
-                store(f, pa.phi, item_off);
+                const float t1 = mix0[0].x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) hmix_group<CF, G0, false, 0>(f[t], xb, tau, t1, pm);
+                if constexpr (PAIR) hflip(f[0], f[1], t1);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    hxpose<CF, RL, RIO>(f[t], xb, tau);
+                    store(f[t], pa.phi, off[t], t);
+                }
                 continue;
             }
         }
         if constexpr (KIND == FWD_MIX || KIND == FWD_BND_MIX || KIND == FWD_BND_FINAL || KIND == GR_BND_FINAL) {
-            load(f, pa.phi, item_off);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) load(f[t], pa.phi, off[t], t);
             const float2 tka = mix0[pa.la - 1];
-            hmix_group<GR, G0, true, RIO>(f, xb, tau, tka.x, pm);     // ends in rotation 0
+#pragma unroll
+            for (int t = 0; t < NT; ++t) hmix_group<CF, G0, true, RIO>(f[t], xb, tau, tka.x, pm);   // ends in rotation 0
+            if constexpr (PAIR) hflip(f[0], f[1], tka.x);
             if constexpr (KIND == FWD_MIX) {
-                hxpose<GR, 0, RIO>(f, xb, tau);
-                store(f, pa.phi, item_off);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    hxpose<CF, 0, RIO>(f[t], xb, tau);
+                    store(f[t], pa.phi, off[t], t);
+                }
                 continue;
             }
-            phase_stage(f, pk0, rows + (pa.lb - 1) * pa.rowcap, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                phase_stage(f[t], pk[t], rows + (pa.lb - 1) * pa.rowcap, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
             if constexpr (KIND == FWD_BND_MIX) {
-                hmix_group<GR, G0, false, 0>(f, xb, tau, mix0[pa.lb - 1].x, pm);
-                hxpose<GR, RL, RIO>(f, xb, tau);
-                store(f, pa.phi, item_off);
+                const float tb = mix0[pa.lb - 1].x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) hmix_group<CF, G0, false, 0>(f[t], xb, tau, tb, pm);
+                if constexpr (PAIR) hflip(f[0], f[1], tb);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    hxpose<CF, RL, RIO>(f[t], xb, tau);
+                    store(f[t], pa.phi, off[t], t);
+                }
                 continue;
             }
         }
         // ------------------------------------------------------------ final layer
         if constexpr (FINAL) {
             const float tp = mix0[p - 1].x;
-#pragma unroll
-            for (int r = 0; r < A; ++r)
-                if (!(r & 1)) bfly(f[r], f[r | 1], tp);
-#pragma unroll
-            for (int r = 0; r < A; ++r)
-                if (!(r & 2)) bfly(f[r], f[r | 2], tp);
             double zzp = 0.0;
 #pragma unroll
-            for (int r = 0; r < A; ++r) {
-                const double pr = static_cast<double>(fmaf(f[r].x, f[r].x, f[r].y * f[r].y));
-                zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
+            for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                for (int r = 0; r < A; ++r)
+                    if (!(r & 1)) bfly(f[t][r], f[t][r | 1], tp);
+#pragma unroll
+                for (int r = 0; r < A; ++r)
+                    if (!(r & 2)) bfly(f[t][r], f[t][r | 2], tp);
+#pragma unroll
+                for (int r = 0; r < A; ++r) {
+                    const double pr = static_cast<double>(fmaf(f[t][r].x, f[t][r].x, f[t][r].y * f[t][r].y));
+                    zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
+                }
             }
             part[0] += zzp;
             if constexpr (GR) {
-                float2 lm[A];
-#pragma unroll
-                for (int r = 0; r < A; ++r) lm[r] = (((r ^ (r >> 1)) & 1) ? make_float2(-f[r].x, -f[r].y) : f[r]);
+                float2 lm[NT][A];
                 float acc = 0.f;
 #pragma unroll
-                for (int r = 0; r < A; ++r)
-                    if (!(r & 1)) xacc(acc, lm[r], lm[r | 1], f[r], f[r | 1]);
+                for (int t = 0; t < NT; ++t) {
 #pragma unroll
-                for (int r = 0; r < A; ++r)
-                    if (!(r & 2)) xacc(acc, lm[r], lm[r | 2], f[r], f[r | 2]);
+                    for (int r = 0; r < A; ++r)
+                        lm[t][r] = (((r ^ (r >> 1)) & 1) ? make_float2(-f[t][r].x, -f[t][r].y) : f[t][r]);
+#pragma unroll
+                    for (int r = 0; r < A; ++r)
+                        if (!(r & 1)) xacc(acc, lm[t][r], lm[t][r | 1], f[t][r], f[t][r | 1]);
+#pragma unroll
+                    for (int r = 0; r < A; ++r)
+                        if (!(r & 2)) xacc(acc, lm[t][r], lm[t][r | 2], f[t][r], f[t][r | 2]);
+#pragma unroll
+                    for (int r = 0; r < A; ++r)
+                        if (!(r & 2)) { bfly(f[t][r], f[t][r | 2], -tp); bfly(lm[t][r], lm[t][r | 2], -tp); }
+#pragma unroll
+                    for (int r = 0; r < A; ++r)
+                        if (!(r & 1)) { bfly(f[t][r], f[t][r | 1], -tp); bfly(lm[t][r], lm[t][r | 1], -tp); }
+                }
                 part[1] += 2.0 * static_cast<double>(acc);
-#pragma unroll
-                for (int r = 0; r < A; ++r)
-                    if (!(r & 2)) { bfly(f[r], f[r | 2], -tp); bfly(lm[r], lm[r | 2], -tp); }
-#pragma unroll
-                for (int r = 0; r < A; ++r)
-                    if (!(r & 1)) { bfly(f[r], f[r | 1], -tp); bfly(lm[r], lm[r | 1], -tp); }
                 const float mu = k2p;
                 if constexpr (KIND == GR_GEN_FINAL) {
-                    const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
+                    float a = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], rows, cd.cut_min, 1.f);
                     part[2] += 2.0 * static_cast<double>(mu) * mu * a;
                 } else {
-                    const float a = cgrad_stage<true>(f, lm, pk0, rows + (p - 1) * pa.rowcap, cd.cut_min, mu);
+                    float a = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        a += cgrad_stage<true>(f[t], lm[t], pk[t], rows + (p - 1) * pa.rowcap, cd.cut_min, mu);
                     part[2] += 2.0 * static_cast<double>(mu) * mu * a;
                     // undo mixer la = p-1 on this group (state sits in rotation 0)
                     const float2 tka = mix0[pa.la - 1];
-                    float w = exp2f(pa.m0a * log2f(tka.y));
-                    const float b = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, w, pm);
+                    const float w0 = exp2f(pa.m0a * log2f(tka.y));
+                    float w = w0, b = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        w = w0;
+                        b += hunmix_group<CF, G0, false, 0>(f[t], lm[t], xb, tau, tka.x, tka.y, w, pm);
+                    }
+                    if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tka.x, tka.y, w);
                     part[3] += 2.0 * static_cast<double>(b);
-                    hxpose<GR, RL, RIO>(lm, xb, tau);
-                    store(lm, pa.lam, item_off);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        hxpose<CF, RL, RIO>(lm[t], xb, tau);
+                        store(lm[t], pa.lam, off[t], t);
+                    }
                 }
             }
         }
         // ------------------------------------------------------------ reverse passes
         if constexpr (KIND == RV_GEN_MIX || KIND == RV_MIX || KIND == RV_BND_MIX) {
-            float2 lm[A];
-            load(f, pa.phi, item_off);
-            load(lm, pa.lam, item_off);
+            float2 lm[NT][A];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                load(f[t], pa.phi, off[t], t);
+                load(lm[t], pa.lam, off[t], t);
+            }
             if (pa.fix_layer > 0) {
                 // The first reverse pass reads psi as the forward sweep left it: the final pass
-                // mixed layer p-1 on group 0 (13 qubits) forward but lambda has undone them,
-                // and the factored mixer scales by 1/|kappa| per qubit in both directions, so
-                // psi carries |kappa|^(k-13) where lambda carries |kappa|^13.
+                // mixed layer p-1 on group 0 (14 qubits with the dropped one) forward but
+                // lambda has undone them, and the factored mixer scales by 1/|kappa| per qubit
+                // in both directions, so psi carries |kappa|^(k-14) where lambda carries
+                // |kappa|^14.
                 const float sc = exp2f(0.5f * pa.fix_pow * log2f(mix0[pa.fix_layer - 1].y));
 #pragma unroll
-                for (int r = 0; r < A; ++r) f[r] = make_float2(sc * f[r].x, sc * f[r].y);
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < A; ++r) f[t][r] = make_float2(sc * f[t][r].x, sc * f[t][r].y);
             }
             if constexpr (KIND == RV_MIX) {
                 const float2 tka = mix0[pa.la - 1];
-                float w = exp2f(pa.m0a * log2f(tka.y));
-                const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tka.x, tka.y, w, pm);
+                const float w0 = exp2f(pa.m0a * log2f(tka.y));
+                float w = w0, b = 0.f;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    w = w0;
+                    b += hunmix_group<CF, G0, true, RIO>(f[t], lm[t], xb, tau, tka.x, tka.y, w, pm);
+                }
+                if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tka.x, tka.y, w);
                 part[0] += 2.0 * static_cast<double>(b);
-                hxpose<GR, 0, RIO>(f, xb, tau);
-                hxpose<GR, 0, RIO>(lm, xb, tau);
-                store(f, pa.phi, item_off);
-                store(lm, pa.lam, item_off);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    hxpose<CF, 0, RIO>(f[t], xb, tau);
+                    hxpose<CF, 0, RIO>(lm[t], xb, tau);
+                    store(f[t], pa.phi, off[t], t);
+                    store(lm[t], pa.lam, off[t], t);
+                }
             } else {
                 // undo mixer lb (the first group of layer lb in forward order: after it, layer
                 // lb is completely undone), then gamma_lb
                 const float2 tkb = mix0[pa.lb - 1];
-                float w = exp2f(pa.m0b * log2f(tkb.y));
-                const float b = hunmix_group<GR, G0, true, RIO>(f, lm, xb, tau, tkb.x, tkb.y, w, pm);
+                const float w0 = exp2f(pa.m0b * log2f(tkb.y));
+                float w = w0, b = 0.f;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    w = w0;
+                    b += hunmix_group<CF, G0, true, RIO>(f[t], lm[t], xb, tau, tkb.x, tkb.y, w, pm);
+                }
+                if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tkb.x, tkb.y, w);
                 part[0] += 2.0 * static_cast<double>(b);
                 const float mu = (pa.lb == p) ? k2p : kpowK(tkb.y);
                 if constexpr (KIND == RV_GEN_MIX) {
-                    const float a = cgrad_stage<false>(f, lm, pk0, rows, cd.cut_min, 1.f);
+                    float a = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], rows, cd.cut_min, 1.f);
                     part[1] += 2.0 * static_cast<double>(mu) * mu * a;
                 } else {
-                    const float a = cgrad_stage<true>(f, lm, pk0, rows + (pa.lb - 1) * pa.rowcap, cd.cut_min, mu);
+                    float a = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        a += cgrad_stage<true>(f[t], lm[t], pk[t], rows + (pa.lb - 1) * pa.rowcap, cd.cut_min, mu);
                     part[1] += 2.0 * static_cast<double>(mu) * mu * a;
                     const float2 tka = mix0[pa.la - 1];
-                    float wa = exp2f(pa.m0a * log2f(tka.y));
-                    const float ba = hunmix_group<GR, G0, false, 0>(f, lm, xb, tau, tka.x, tka.y, wa, pm);
+                    const float wa0 = exp2f(pa.m0a * log2f(tka.y));
+                    float wa = wa0, ba = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        wa = wa0;
+                        ba += hunmix_group<CF, G0, false, 0>(f[t], lm[t], xb, tau, tka.x, tka.y, wa, pm);
+                    }
+                    if constexpr (PAIR) ba += hunflip2(f[0], f[1], lm[0], lm[1], tka.x, tka.y, wa);
                     part[2] += 2.0 * static_cast<double>(ba);
-                    hxpose<GR, RL, RIO>(f, xb, tau);
-                    hxpose<GR, RL, RIO>(lm, xb, tau);
-                    store(f, pa.phi, item_off);
-                    store(lm, pa.lam, item_off);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        hxpose<CF, RL, RIO>(f[t], xb, tau);
+                        hxpose<CF, RL, RIO>(lm[t], xb, tau);
+                        store(f[t], pa.phi, off[t], t);
+                        store(lm[t], pa.lam, off[t], t);
+                    }
                 }
             }
         }
     }
-    double* gp = pa.gpart + (static_cast<size_t>(bslot) * tiles + tile0) * (2 * p + 1);
+    double* gp = pa.gpart + (static_cast<size_t>(bslot) * tiles + unit0) * (2 * p + 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         if (slot[i] >= 0) {

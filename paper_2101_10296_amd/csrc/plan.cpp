@@ -74,7 +74,7 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
     if (p < 1) fail(kEINVAL, "p must be >= 1");
     if (n_gen < 0 || (n_gen > 0 && !gens)) fail(kEINVAL, "bad generator array");
     if (opt.max_cone_qubits < 2 || opt.max_cone_qubits > 30) fail(kEINVAL, "max_cone_qubits must be in [2, 30]");
-    if (opt.k_lds_max < 13 || opt.k_lds_max > 14) fail(kEINVAL, "k_lds_max must be 13 or 14");
+    if (opt.k_lds_max != 14) fail(kEINVAL, "k_lds_max must be 14 (cones above it are kept in device memory)");
 
     P = HostPlan{};
     P.n = n;

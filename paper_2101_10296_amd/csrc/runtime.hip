@@ -38,9 +38,9 @@ qaoa_status grow(T*& ptr, size_t& cap, size_t need, std::string& msg) {
     return QAOA_OK;
 }
 
-// Pass groups of a k-qubit HBM cone: group 0 = qubits 0..12, group j >= 1 = nine of the
-// remaining qubits; tile bit i of group g maps to global bit hbm_group_global_bit(k, g, i)
-// (the same map as hgroup_bits in hbm_impl.hpp).
+// Pass groups over the kh = k - 1 stored qubits of a k-qubit HBM cone: group 0 = qubits
+// 0..12, group j >= 1 = nine of the remaining qubits; tile bit i of group g maps to global
+// bit hbm_group_global_bit(kh, g, i) (the same map as hgroup_bits in hbm_impl.hpp).
 int hbm_group_global_bit(int k, int grp, int i) {
     if (grp == 0) return i;
     const int lo = 13 + 9 * (grp - 1);
@@ -60,14 +60,17 @@ int hbm_group_qubits(int k, int grp) {
     return std::min(k, lo + 9) - lo;
 }
 
-// Forward program: layer l (1 <= l <= p-1) visits the groups in descending order when
-// p-1-l is even, ascending otherwise, so layer p-1 ends on group 0 and consecutive layers
-// share a pass.  With grad, the last pass is the fused final/adjoint pass and the earlier
-// passes follow in reverse as RV_* passes; m0a / m0b count the qubits of a layer already
-// undone by earlier reverse passes.
+// Forward program over the stored qubits (kh = k - 1): layer l (1 <= l <= p-1) visits the
+// groups in descending order when p-1-l is even, ascending otherwise, so layer p-1 ends on
+// group 0 and consecutive layers share a pass.  Group-0 passes also mix the dropped qubit
+// k-1 (14 qubits per layer).  With grad, the last pass is the fused final/adjoint pass and
+// the earlier passes follow in reverse as RV_* passes; m0a / m0b count the qubits of a
+// layer already undone by earlier reverse passes.
 std::vector<PassSpec> hbm_program(int k, int p, bool grad) {
     std::vector<PassSpec> fwd;
-    const int n = hbm_groups_of(k);
+    const int kh = k - 1;
+    const int n = hbm_groups_of(kh);
+    auto layer_qubits = [&](int g) { return hbm_group_qubits(kh, g) + (g == 0 ? 1 : 0); };
     if (p == 1) {
         fwd.push_back({grad ? GR_GEN_FINAL : FWD_GEN_FINAL, 0, 0, 1, 0, 0, 0, 0});
         return fwd;
@@ -87,11 +90,11 @@ std::vector<PassSpec> hbm_program(int k, int p, bool grad) {
     PassSpec fin = fwd.back();
     fin.kind = GR_BND_FINAL;
     fin.m0a = undone[fin.la];
-    undone[fin.la] += hbm_group_qubits(k, fin.group);
+    undone[fin.la] += layer_qubits(fin.group);
     out.push_back(fin);
     for (int i = static_cast<int>(fwd.size()) - 2; i >= 0; --i) {
         PassSpec r = fwd[i];
-        const int h = hbm_group_qubits(k, r.group);
+        const int h = layer_qubits(r.group);
         if (r.kind == FWD_GEN_MIX) {
             r.kind = RV_GEN_MIX;
             r.m0b = undone[r.lb];
@@ -109,7 +112,7 @@ std::vector<PassSpec> hbm_program(int k, int p, bool grad) {
         }
         if (i == static_cast<int>(fwd.size()) - 2) {
             r.fix_layer = fin.la;
-            r.fix_pow = k - 2 * hbm_group_qubits(k, 0);
+            r.fix_pow = k - 2 * layer_qubits(0);
         }
         out.push_back(r);
     }
@@ -181,12 +184,12 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         d.cut_min = c.cut_min;
         d.cut_range = c.cut_max - c.cut_min + 1;
         d.cut_shift = c.cut_min - hp.cut_min;
-        d.n_groups = hbm_groups_of(c.k);
+        d.n_groups = hbm_groups_of(c.k - 1);
         max_groups = std::max(max_groups, d.n_groups);
         for (int g = 0; g < d.n_groups; ++g) {
             // tile bits of group g; C_tt ranges over the edges with both ends inside
             std::vector<char> in(32, 0);
-            for (int i = 0; i < 13; ++i) in[hbm_group_global_bit(c.k, g, i)] = 1;
+            for (int i = 0; i < 13; ++i) in[hbm_group_global_bit(c.k - 1, g, i)] = 1;
             int32_t tmin = 0, tmax = 0;
             for (size_t e = 0; e < c.ea.size(); ++e)
                 if (in[c.ea[e]] && in[c.eb[e]]) (c.ew[e] < 0 ? tmin : tmax) += c.ew[e];
@@ -325,14 +328,14 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
     if (!fixed_batches) P->hbm_batch.assign(P->hbm_groups.size(), 0);
     for (size_t gi = 0; gi < P->hbm_groups.size(); ++gi) {
         const auto& grp = P->hbm_groups[gi];
-        const int k = grp.K;
+        const int k = grp.K, kh = k - 1;      // stored qubits: the half with qubit k-1 = 0
         const int64_t items = grp.count * n_points;
-        const int64_t tiles = int64_t{1} << (k - HT);
+        const int64_t tiles = int64_t{1} << (kh - HT);
         const int nvals = grad ? 2 * p + 1 : 1;     // values reduced per item
         const int stride = 2 * p + 1;                // values stored per (item, tile)
         const bool need_phi = p >= 2;
         const bool need_lam = grad && p >= 2;
-        const size_t state_bytes = (size_t{1} << k) * sizeof(float2);
+        const size_t state_bytes = (size_t{1} << kh) * sizeof(float2);
         const size_t per_item = (need_phi ? state_bytes : 0) + (need_lam ? state_bytes : 0) +
                                 static_cast<size_t>(tiles) * stride * sizeof(double);
         size_t budget = static_cast<size_t>(P->opt.mem_budget_bytes);
@@ -355,8 +358,8 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         // the batch is halved until one item does not fit either
         for (;;) {
             st = QAOA_OK;
-            if (need_phi) st = grow(P->d_phi, P->cap_phi, static_cast<size_t>(B) << k, msg);
-            if (st == QAOA_OK && need_lam) st = grow(P->d_lam, P->cap_lam, static_cast<size_t>(B) << k, msg);
+            if (need_phi) st = grow(P->d_phi, P->cap_phi, static_cast<size_t>(B) << kh, msg);
+            if (st == QAOA_OK && need_lam) st = grow(P->d_lam, P->cap_lam, static_cast<size_t>(B) << kh, msg);
             if (st == QAOA_OK) st = grow(P->d_gpart, P->cap_gpart, static_cast<size_t>(B) * tiles * stride, msg);
             if (st != QAOA_ENOMEM || B == 1) break;
             for (float2** b : {&P->d_phi, &P->d_lam}) {
@@ -369,10 +372,11 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         if (st != QAOA_OK) return st;
         P->hbm_batch[gi] = B;
         const std::vector<PassSpec> prog = hbm_program(k, p, grad);
-        // tiles per workgroup: up to 8 while the class keeps >= 4096 workgroups (16 per CU);
-        // fixed per class, so an item's sums run in the same order whatever the batching
+        // tiles (group 0: tile pairs) per workgroup: up to 8 while the class keeps >= 4096
+        // workgroups (16 per CU); fixed per class, so an item's sums run in the same order
+        // whatever the batching
         int tpw = 1;
-        while (tpw < 8 && 2 * tpw <= tiles && items * tiles / (2 * tpw) >= 4096) tpw *= 2;
+        while (tpw < 8 && 2 * tpw <= tiles / 2 && items * tiles / (2 * tpw) >= 4096) tpw *= 2;
         QCHECK(tm.begin(k, items));
         for (int64_t i0 = 0; i0 < items; i0 += B) {
             const int64_t nb = std::min<int64_t>(B, items - i0);
@@ -390,6 +394,7 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
                 pa.item0 = i0;
                 pa.n_batch = static_cast<int32_t>(nb);
                 pa.k = k;
+                pa.kh = kh;
                 pa.group = ps.group;
                 pa.la = ps.la;
                 pa.lb = ps.lb;

@@ -1,8 +1,8 @@
 """GPU parity of cones held in device memory (more than k_lds_max qubits) against the oracle.
 
 Same tolerances as test_gpu_parity.py.  Covered: two and three pass groups, depths 1-3,
-the p = 1 path that needs no state buffers, reduced plans, batching under a small memory
-budget, and agreement with the workgroup-resident kernel on 14-qubit cones.
+the p = 1 path that needs no state buffers, the smallest device-memory cones (15 and 16
+qubits: one and two tile pairs), reduced plans and batching under a small memory budget.
 """
 import numpy as np
 import pytest
@@ -23,26 +23,23 @@ def Q():
     return Q
 
 
-def test_hbm_matches_workgroup_kernel_on_14_qubit_cones(Q):
-    g = W.random_regular(30, 3, 5)
-    ga, be = W.draw_angles(5, 2, 3)
-    a = Q.Plan(g.n, g.edges, p=2)
-    b = Q.Plan(g.n, g.edges, p=2, k_lds_max=13)
-    assert b.info()["n_hbm_cones"] > 0
-    Ea, dga, dba = a.energy_grad(dev(ga), dev(be))
-    Eb, dgb, dbb = b.energy_grad(dev(ga), dev(be))
-    assert (Ea - Eb).abs().max().item() <= ZZ_TOL * g.m / 2
-    scale = max(dga.abs().max().item(), dba.abs().max().item())
-    assert (dga - dgb).abs().max().item() <= 1e-4 * scale
-    assert (dba - dbb).abs().max().item() <= 1e-4 * scale
-    check_energy(Q, g, 2, ga, be, reduce=False, grad=True, plan_kw=dict(k_lds_max=13))
-
-
 @pytest.mark.parametrize("p", [1, 2, 3])
-def test_hbm_k14_all_depths(Q, p):
-    g = W.star(13)
+@pytest.mark.parametrize("m", [14, 15])
+def test_hbm_star_all_depths(Q, p, m):
+    # star K_{1,m}: one orbit whose cone holds all m + 1 qubits (15 or 16: the smallest
+    # cones kept in device memory, one or two tile pairs of the stored half)
+    g = W.star(m)
     ga, be = W.draw_angles(3, p, 70 + p)
-    check_energy(Q, g, p, ga, be, grad=True, plan_kw=dict(k_lds_max=13))
+    pl, _, _ = check_energy(Q, g, p, ga, be, grad=True)
+    assert pl.info()["n_hbm_cones"] == 1 and pl.info()["max_k"] == m + 1
+
+
+def test_workgroup_and_device_classes_one_plan_p3(Q):
+    # C_40(1,2) at p = 3: a 14-qubit cone (workgroup kernel) and a 15-qubit one (passes)
+    g = W.circulant(40, (1, 2))
+    ga, be = W.draw_angles(3, 3, 17)
+    pl, _, _ = check_energy(Q, g, 3, ga, be, grad=True)
+    assert pl.info()["n_hbm_cones"] == 1 and pl.info()["min_k"] == 14
 
 
 def test_torus_k18_p2_reduced(Q):
