@@ -247,6 +247,56 @@ __device__ __forceinline__ float xpose2_unflip(float2 (&f)[A], float2 (&l)[A], f
     return acc;
 }
 
+// Two-buffer forms for the adjoint kernels that run one workgroup per CU (registers limit
+// them there, so LDS has room for a second buffer): psi and lambda go through LDS together,
+// one barrier pair instead of two.
+template <int K, int G, int FROM, int TO, int A>
+__device__ __forceinline__ void xpose_dual(float2 (&f)[A], float2 (&l)[A], float2* xa, float2* xc, uint32_t tau) {
+    const uint32_t of = opaque_u32(pad(tbase<K, G, FROM>(tau)));
+    const uint32_t ot = opaque_u32(pad(tbase<K, G, TO>(tau)));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        xa[of + pad(roff<K, G, FROM>(r))] = f[r];
+        xc[of + pad(roff<K, G, FROM>(r))] = l[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        f[r] = xa[ot + pad(roff<K, G, TO>(r))];
+        l[r] = xc[ot + pad(roff<K, G, TO>(r))];
+    }
+}
+
+template <int K, int G, int FROM, int TO, int A>
+__device__ __forceinline__ float xpose2_unflip_dual(float2 (&f)[A], float2 (&l)[A], float2* xa, float2* xc,
+                                                    uint32_t tau, float t) {
+    constexpr uint32_t TM = Fz<K, G>::TPI - 1;
+    const uint32_t of = opaque_u32(pad(tbase<K, G, FROM>(tau)));
+    const uint32_t ot = opaque_u32(pad(tbase<K, G, TO>(tau)));
+    const uint32_t oc = opaque_u32(pad(tbase<K, G, TO>(~tau & TM)));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        xa[of + pad(roff<K, G, FROM>(r))] = f[r];
+        xc[of + pad(roff<K, G, FROM>(r))] = l[r];
+    }
+    __syncthreads();
+    float acc = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 fo = xa[ot + pad(roff<K, G, TO>(r))];
+        const float2 fq = xa[oc + pad(roff<K, G, TO>(A - 1 - r))];
+        const float2 lo = xc[ot + pad(roff<K, G, TO>(r))];
+        const float2 lq = xc[oc + pad(roff<K, G, TO>(A - 1 - r))];
+        cacc(acc, 1.f, lo, fq);
+        l[r] = make_float2(fmaf(-t, lq.y, lo.x), fmaf(t, lq.x, lo.y));
+        f[r] = make_float2(fmaf(-t, fq.y, fo.x), fmaf(t, fq.x, fo.y));
+        if ((r & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
 // The same with the whole item in one thread's registers (complement partner A-1-r).
 template <int A>
 __device__ __forceinline__ void reg_flip(float2 (&v)[A], float t) {
@@ -367,9 +417,9 @@ __device__ __forceinline__ void fwd_layer(float2 (&f)[A], float2* xb, uint32_t t
 
 // Undo a forward layer of direction DESC on psi and lambda (stages in reverse order);
 // returns the thread's share of Im <lambda| sum_j X_j |psi>.
-template <int K, int G, bool DESC, bool FLIP, int A>
-__device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t,
-                                          float k2) {
+template <int K, int G, bool DESC, bool FLIP, bool DB, int A>
+__device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2* xb, float2* xb2, uint32_t tau,
+                                          float t, float k2) {
     constexpr int S = Fz<K, G>::S;
     double acc = 0.0;
     float w = 1.f;
@@ -383,8 +433,11 @@ __device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2
         if constexpr (j > 0) {
             constexpr int prev = DESC ? j - 1 : S - j;
             if constexpr (FLIP && j == 1) {
-                acc += static_cast<double>(w * xpose2_unflip<K, G, prev, st>(f, l, xb, tau, t));
+                if constexpr (DB) acc += static_cast<double>(w * xpose2_unflip_dual<K, G, prev, st>(f, l, xb, xb2, tau, t));
+                else acc += static_cast<double>(w * xpose2_unflip<K, G, prev, st>(f, l, xb, tau, t));
                 w *= k2;
+            } else if constexpr (DB) {
+                xpose_dual<K, G, prev, st>(f, l, xb, xb2, tau);
             } else {
                 xpose<K, G, prev, st>(f, xb, tau);
                 xpose<K, G, prev, st>(l, xb, tau);
@@ -421,7 +474,7 @@ __device__ __forceinline__ double item_sum(double x, double* red, int tid) {
 // layer p-1 ends in stage 0 (qubits 0 and 1).  With ODD the first layer is descending and
 // is peeled off; the remaining layers come in (ascending, descending) pairs, so no branch
 // ever selects between the two layer bodies.
-template <int K, bool GRAD, bool ODD>
+template <int K, bool GRAD, bool ODD, bool DB>
 __global__ void __launch_bounds__((Fz<(K >= 3 ? K - 1 : K), (GRAD ? 1 : 0)>::WG))
 k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         const uint8_t* __restrict__ cut_tables, int32_t rowcap, EvalArgs ea) {
@@ -433,7 +486,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     constexpr double HS = FLIP ? 2.0 : 1.0;
     using C = Fz<KL, GI>;
     constexpr int A = C::A;
-    __shared__ float2 xbuf[C::S > 1 ? C::IPW * C::NPAD : 1];
+    __shared__ float2 xbuf[C::S > 1 ? (DB ? 2 : 1) * C::IPW * C::NPAD : 1];
     __shared__ __attribute__((aligned(16))) uint8_t cutl[C::IPW * C::N < 16 ? 16 : C::IPW * C::N];
     __shared__ double red[C::WG / 64];
     extern __shared__ float2 prow_all[];   // [IPW][p][rowcap] phase rows of every layer
@@ -463,6 +516,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     }
     const uint8_t* cut = cutl + il * C::N;
     float2* xb = xbuf + (C::S > 1 ? il * C::NPAD : 0);
+    float2* xb2 = DB ? xbuf + (C::S > 1 ? (C::IPW + il) * C::NPAD : 0) : nullptr;
     const float2* phase0 = ea.phase + static_cast<size_t>(point) * p * ea.R + cd.cut_shift;
     const float2* mix0 = ea.mix + static_cast<size_t>(point) * p;
     {   // phase rows of every layer for this item: prow[il][l][c] = exp(-i gamma_l (cut_min + c))
@@ -570,7 +624,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             }
             {
                 const float2 tk = mix0[ly - 2];
-                const double b = unlayer<KL, GI, true, FLIP>(f, lam, xb, tau, tk.x, tk.y);
+                const double b = unlayer<KL, GI, true, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
                 const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
                 mu = kpowK(tk.y);
@@ -589,7 +643,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             }
             {
                 const float2 tk = mix0[ly - 2];
-                const double b = unlayer<KL, GI, false, FLIP>(f, lam, xb, tau, tk.x, tk.y);
+                const double b = unlayer<KL, GI, false, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
                 const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
                 mu = kpowK(tk.y);
@@ -612,14 +666,35 @@ hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t 
     const size_t dyn = static_cast<size_t>(ipw) * ea.p * rowcap * sizeof(float2);
     const dim3 grid(static_cast<unsigned>(blocks)), block(wg);
     const bool odd = ((ea.p - 1) & 1) != 0;
-    if (grad && odd)
-        hipLaunchKernelGGL((k_fused<K, true, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-    else if (grad)
-        hipLaunchKernelGGL((k_fused<K, true, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-    else if (odd)
-        hipLaunchKernelGGL((k_fused<K, false, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-    else
-        hipLaunchKernelGGL((k_fused<K, false, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    if (grad) {
+        if constexpr (K >= 13) {
+            // two LDS buffers when the phase rows still fit beside them
+            static size_t db_static[2] = {0, 0};
+            const int oi = odd ? 1 : 0;
+            if (!db_static[oi]) {
+                hipFuncAttributes fa{};
+                const hipError_t e = odd ? hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, true, true, true>))
+                                         : hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, true, false, true>));
+                if (e != hipSuccess) return e;
+                db_static[oi] = fa.sharedSizeBytes;
+            }
+            if (db_static[oi] + dyn <= 160 * 1024) {
+                if (odd)
+                    hipLaunchKernelGGL((k_fused<K, true, true, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+                else
+                    hipLaunchKernelGGL((k_fused<K, true, false, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+                return hipGetLastError();
+            }
+        }
+        if (odd)
+            hipLaunchKernelGGL((k_fused<K, true, true, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+        else
+            hipLaunchKernelGGL((k_fused<K, true, false, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    } else if (odd) {
+        hipLaunchKernelGGL((k_fused<K, false, true, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    } else {
+        hipLaunchKernelGGL((k_fused<K, false, false, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
+    }
     return hipGetLastError();
 }
 
