@@ -76,7 +76,22 @@ static hipError_t launch_one(const PassArgs& pa, hipStream_t st) {
     if (pa.tpw < 1 || units % pa.tpw != 0) return hipErrorInvalidValue;
     const int64_t blocks = units * pa.n_batch / pa.tpw;
     const size_t dyn = static_cast<size_t>(pa.ea.p) * pa.rowcap * sizeof(float2);
-    hipLaunchKernelGGL((k_pass<KIND, G0>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<CF>::W), dyn, st, pa);
+    if constexpr (CF == 3) {
+        // two LDS buffers when the phase rows still fit beside them
+        static size_t db_static = 0;
+        if (!db_static) {
+            hipFuncAttributes fa{};
+            const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_pass<KIND, G0, true>));
+            if (e != hipSuccess) return e;
+            db_static = fa.sharedSizeBytes;
+        }
+        if (db_static + dyn <= 160 * 1024) {
+            hipLaunchKernelGGL((k_pass<KIND, G0, true>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<CF>::W), dyn, st,
+                               pa);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_pass<KIND, G0, false>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<CF>::W), dyn, st, pa);
     return hipGetLastError();
 }
 

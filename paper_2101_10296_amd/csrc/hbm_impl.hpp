@@ -141,6 +141,25 @@ __device__ __forceinline__ void hxpose(float2 (&v)[A], float2* xb, uint32_t tau)
     for (int r = 0; r < A; ++r) v[r] = pt[pad(hroff<CF, RT>(r))];
 }
 
+// psi and lambda through two LDS buffers at once (one barrier pair instead of two).
+template <int CF, int RF, int RT, int A>
+__device__ __forceinline__ void hxpose_dual(float2 (&f)[A], float2 (&l)[A], float2* xa, float2* xc, uint32_t tau) {
+    const uint32_t of = opaque_u32(pad(htbase<CF, RF>(tau)));
+    const uint32_t ot = opaque_u32(pad(htbase<CF, RT>(tau)));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        xa[of + pad(hroff<CF, RF>(r))] = f[r];
+        xc[of + pad(hroff<CF, RF>(r))] = l[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        f[r] = xa[ot + pad(hroff<CF, RT>(r))];
+        l[r] = xc[ot + pad(hroff<CF, RT>(r))];
+    }
+}
+
 // Mixer on the processed tile bits of layout ROT (tile bit b is processed when bit b of
 // pm is set; a butterfly with tau = 0 is the identity).  Wrapped bits belong to rotation 0.
 template <int CF, int ROT, int A>
@@ -217,9 +236,9 @@ __device__ __forceinline__ void hmix_group(float2 (&f)[A], float2* xb, uint32_t 
     });
 }
 
-template <int CF, bool G0, bool DESC, int FROM_ROT, int A>
+template <int CF, bool G0, bool DESC, int FROM_ROT, bool DB = false, int A>
 __device__ __forceinline__ float hunmix_group(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t,
-                                              float k2, float& w, uint32_t pm) {
+                                              float k2, float& w, uint32_t pm, float2* xb2 = nullptr) {
     using H = HStages<CF, G0>;
     float acc = 0.f;
     static_for<0, H::S>([&](auto J) {
@@ -227,8 +246,12 @@ __device__ __forceinline__ float hunmix_group(float2 (&f)[A], float2 (&l)[A], fl
         constexpr int st = DESC ? H::S - 1 - j : j;
         constexpr int prev = (j == 0) ? FROM_ROT : H::rot(DESC ? H::S - j : j - 1);
         if constexpr (prev != H::rot(st)) {
-            hxpose<CF, prev, H::rot(st)>(f, xb, tau);
-            hxpose<CF, prev, H::rot(st)>(l, xb, tau);
+            if constexpr (DB) {
+                hxpose_dual<CF, prev, H::rot(st)>(f, l, xb, xb2, tau);
+            } else {
+                hxpose<CF, prev, H::rot(st)>(f, xb, tau);
+                hxpose<CF, prev, H::rot(st)>(l, xb, tau);
+            }
         }
         acc += hunmix2<CF, H::rot(st)>(f, l, t, k2, w, pm);
     });
@@ -286,7 +309,9 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
     return s;
 }
 
-template <int KIND, bool G0>
+// DB: two LDS buffers (psi and lambda transposed together) for the adjoint tile-pair
+// passes, which run one workgroup per CU anyway (registers).
+template <int KIND, bool G0, bool DB = false>
 __global__ void __launch_bounds__((Hz<pass_cf(KIND, G0)>::W), (Hz<pass_cf(KIND, G0)>::WPE))
 k_pass(PassArgs pa) {
     constexpr int CF = pass_cf(KIND, G0);
@@ -299,7 +324,7 @@ k_pass(PassArgs pa) {
     constexpr int NW = (A + 3) / 4;
     constexpr bool FINAL = (KIND == FWD_GEN_FINAL || KIND == FWD_BND_FINAL || KIND == GR_GEN_FINAL ||
                             KIND == GR_BND_FINAL);
-    __shared__ float2 xbuf[H::NPAD];
+    __shared__ float2 xbuf[(DB ? 2 : 1) * H::NPAD];
     __shared__ __attribute__((aligned(16))) uint8_t ttl[HN];
     __shared__ int32_t lcoef[NT][HT];
     __shared__ double red[H::W / 64];
@@ -398,6 +423,7 @@ k_pass(PassArgs pa) {
             *reinterpret_cast<float2*>(reinterpret_cast<char*>(buf + off + io_off(t ? A - 1 - r : r)) + tb) = v[r];
     };
     float2* xb = xbuf;
+    float2* xb2 = DB ? xbuf + H::NPAD : nullptr;
     const float2* mix0 = pa.ea.mix + static_cast<size_t>(point) * p;
     auto kpowK = [&](float k2) { return exp2f(0.5f * k * log2f(k2)); };
     const float k2p = mix0[p - 1].y;
@@ -604,7 +630,7 @@ k_pass(PassArgs pa) {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         w = w0;
-                        b += hunmix_group<CF, G0, false, 0>(f[t], lm[t], xb, tau, tka.x, tka.y, w, pm);
+                        b += hunmix_group<CF, G0, false, 0, DB>(f[t], lm[t], xb, tau, tka.x, tka.y, w, pm, xb2);
                     }
                     if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tka.x, tka.y, w);
                     part[3] += 2.0 * static_cast<double>(b);
@@ -643,14 +669,18 @@ k_pass(PassArgs pa) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     w = w0;
-                    b += hunmix_group<CF, G0, true, RIO>(f[t], lm[t], xb, tau, tka.x, tka.y, w, pm);
+                    b += hunmix_group<CF, G0, true, RIO, DB>(f[t], lm[t], xb, tau, tka.x, tka.y, w, pm, xb2);
                 }
                 if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tka.x, tka.y, w);
                 part[0] += 2.0 * static_cast<double>(b);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    hxpose<CF, 0, RIO>(f[t], xb, tau);
-                    hxpose<CF, 0, RIO>(lm[t], xb, tau);
+                    if constexpr (DB) {
+                        hxpose_dual<CF, 0, RIO>(f[t], lm[t], xb, xb2, tau);
+                    } else {
+                        hxpose<CF, 0, RIO>(f[t], xb, tau);
+                        hxpose<CF, 0, RIO>(lm[t], xb, tau);
+                    }
                     store(f[t], pa.phi, off[t], t);
                     store(lm[t], pa.lam, off[t], t);
                 }
@@ -663,7 +693,7 @@ k_pass(PassArgs pa) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     w = w0;
-                    b += hunmix_group<CF, G0, true, RIO>(f[t], lm[t], xb, tau, tkb.x, tkb.y, w, pm);
+                    b += hunmix_group<CF, G0, true, RIO, DB>(f[t], lm[t], xb, tau, tkb.x, tkb.y, w, pm, xb2);
                 }
                 if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tkb.x, tkb.y, w);
                 part[0] += 2.0 * static_cast<double>(b);
@@ -685,14 +715,18 @@ k_pass(PassArgs pa) {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         wa = wa0;
-                        ba += hunmix_group<CF, G0, false, 0>(f[t], lm[t], xb, tau, tka.x, tka.y, wa, pm);
+                        ba += hunmix_group<CF, G0, false, 0, DB>(f[t], lm[t], xb, tau, tka.x, tka.y, wa, pm, xb2);
                     }
                     if constexpr (PAIR) ba += hunflip2(f[0], f[1], lm[0], lm[1], tka.x, tka.y, wa);
                     part[2] += 2.0 * static_cast<double>(ba);
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
-                        hxpose<CF, RL, RIO>(f[t], xb, tau);
-                        hxpose<CF, RL, RIO>(lm[t], xb, tau);
+                        if constexpr (DB) {
+                            hxpose_dual<CF, RL, RIO>(f[t], lm[t], xb, xb2, tau);
+                        } else {
+                            hxpose<CF, RL, RIO>(f[t], xb, tau);
+                            hxpose<CF, RL, RIO>(lm[t], xb, tau);
+                        }
                         store(f[t], pa.phi, off[t], t);
                         store(lm[t], pa.lam, off[t], t);
                     }

@@ -132,3 +132,12 @@ def test_stored_oracle_cases(Q, name):
         ref_inf = max(np.abs(dgo[i]).max(), np.abs(dbo[i]).max())
         err = max(np.abs(dg[i] - dgo[i]).max(), np.abs(db[i] - dbo[i]).max())
         assert err <= 1e-4 * max(ref_inf, 1e-3 * Wt), (i, err, ref_inf)
+
+
+@pytest.mark.parametrize("p", [4, 5])
+def test_deep_circuits_device_memory(Q, p):
+    # the 15- and 16-qubit stars at p = 4, 5: several boundary passes per group, both snake
+    # directions, and the first reverse pass's rescale at deeper layers
+    ga, be = W.draw_angles(2, p, 80 + p)
+    for m in (14, 15):
+        check_energy(Q, W.star(m), p, ga, be, grad=True)

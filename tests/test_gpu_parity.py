@@ -201,3 +201,14 @@ def test_input_errors(Q):
     pl = Q.Plan(g.n, g.edges, p=2)
     with pytest.raises(ValueError):
         pl.energy(dev(np.zeros((2, 2))), dev(np.zeros((3, 2))))
+
+
+@pytest.mark.parametrize("p", [4, 5, 6])
+def test_deep_circuits(Q, p):
+    # more layers than the workloads use: both stage orders of the layer loop, many layers
+    # undone by the adjoint; cones of 4-10 qubits and the 6- and 14-qubit stars
+    g = W.random_regular(10, 3, 5)
+    ga, be = W.draw_angles(2, p, 60 + p)
+    check_energy(Q, g, p, ga, be, reduce=False, grad=True)
+    for m in (5, 13):
+        check_energy(Q, W.star(m), p, ga, be, grad=True)
