@@ -357,7 +357,12 @@ def main():
     if a.copy_gib > 0:
         line["copy"] = copy_measure(torch, a.copy_gib)
     if not a.no_cpu_baseline:
-        v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
+        try:   # the oracle is element-wise numpy (one thread); pin any BLAS pool to one thread too
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(1):
+                v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
+        except ImportError:
+            v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
         line["cpu_baseline"] = {"value": round(v, 6), "unit": "evals/s", "cores": 1, "kind": "oracle",
                                 "sample": sample + f" (FP64 numpy, {cpu_model()}, extrapolated to all terms)"}
     print(json.dumps(line), flush=True)
