@@ -324,6 +324,7 @@ k_pass(PassArgs pa) {
     constexpr int NW = (A + 3) / 4;
     constexpr bool FINAL = (KIND == FWD_GEN_FINAL || KIND == FWD_BND_FINAL || KIND == GR_GEN_FINAL ||
                             KIND == GR_BND_FINAL);
+    constexpr bool CUTS = !(KIND == FWD_MIX || KIND == RV_MIX);   // phases or C inner products
     __shared__ float2 xbuf[(DB ? 2 : 1) * H::NPAD];
     __shared__ __attribute__((aligned(16))) uint8_t ttl[HN];
     __shared__ int32_t lcoef[NT][HT];
@@ -352,8 +353,8 @@ k_pass(PassArgs pa) {
     for (int i = 0; i < HT; ++i) tmask |= 1u << hgroup_bits(kh, pa.group, i, h);
     const uint32_t pm = (pa.group == 0) ? (HN - 1u) : ((1u << h) - 1u);
     const int32_t k0_base = pa.cones[cslot].tt_min[pa.group] - cd.cut_min;
-    if (tid < 32) tpos[tid] = -1;
-    {
+    if (CUTS && tid < 32) tpos[tid] = -1;
+    if constexpr (CUTS) {
         const uint8_t* src = pa.tt + pa.cones[cslot].tt_off[pa.group];
         for (uint32_t q = tau * 16; q < HN; q += H::W * 16)
             *reinterpret_cast<uint4*>(ttl + q) = *reinterpret_cast<const uint4*>(src + q);
@@ -363,13 +364,13 @@ k_pass(PassArgs pa) {
                 rows[l * pa.rowcap + c] = ph0[static_cast<size_t>(l) * pa.ea.R + c];
     }
     __syncthreads();
-    if (tid < HT) {
+    if (CUTS && tid < HT) {
         int hh;
         tpos[hgroup_bits(kh, pa.group, tid, hh)] = static_cast<int8_t>(tid);
     }
     // the thread's first cone edge, kept in registers for every tile
     int e0a = 0, e0b = 0, e0w = 0;
-    if (tid < cd.n_edges) {
+    if (CUTS && tid < cd.n_edges) {
         e0a = pa.e_a[cd.edge_off + tid];
         e0b = pa.e_b[cd.edge_off + tid];
         e0w = pa.e_w[cd.edge_off + tid];
@@ -448,6 +449,17 @@ k_pass(PassArgs pa) {
         slot[0] = p + pa.lb; slot[1] = pa.lb; slot[2] = p + pa.la;
     }
 
+    auto outer_of = [&](int64_t tile) {
+        uint64_t x = 0;
+        int64_t o = tile;
+        for (int b = 0; b < kh; ++b)
+            if (!((tmask >> b) & 1u)) {
+                x |= static_cast<uint64_t>(o & 1) << b;
+                o >>= 1;
+            }
+        return x;
+    };
+
     for (int64_t unit = unit0; unit < unit0 + pa.tpw; ++unit) {
         // ---- outer bits of the unit's tiles and their linear cut coefficients: an edge
         // between tile bit b and an outer bit o adds w (1 - 2 x_o) to lcoef[b] and w x_o to
@@ -455,66 +467,59 @@ k_pass(PassArgs pa) {
         // exact in any order).  Qubit k-1 is an outer bit fixed at 0.
         uint64_t xo[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int64_t tile = t ? tiles - 1 - unit : unit;
-            int64_t o = tile;
-            xo[t] = 0;
-            for (int b = 0; b < kh; ++b)
-                if (!((tmask >> b) & 1u)) {
-                    xo[t] |= static_cast<uint64_t>(o & 1) << b;
-                    o >>= 1;
+        for (int t = 0; t < NT; ++t) xo[t] = outer_of(t ? tiles - 1 - unit : unit);
+        uint32_t pk[NT][NW];
+        if constexpr (CUTS) {
+            __syncthreads();   // the previous unit has read lcoef and k0
+            if (tid < HT) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) lcoef[t][tid] = 0;
+            }
+            if (tid == 0) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) k0_sh[t] = k0_base;
+            }
+            __syncthreads();
+            auto add_edge = [&](int a, int b, int w) {
+                const int ia = tpos[a], ib = tpos[b];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int xa = static_cast<int>((xo[t] >> a) & 1u), xb2 = static_cast<int>((xo[t] >> b) & 1u);
+                    if (ia >= 0 && ib < 0) {
+                        atomicAdd(&lcoef[t][ia], w - 2 * w * xb2);
+                        if (xb2) atomicAdd(&k0_sh[t], w);
+                    } else if (ia < 0 && ib >= 0) {
+                        atomicAdd(&lcoef[t][ib], w - 2 * w * xa);
+                        if (xa) atomicAdd(&k0_sh[t], w);
+                    } else if (ia < 0 && ib < 0 && (xa ^ xb2)) {
+                        atomicAdd(&k0_sh[t], w);
+                    }
                 }
-        }
-        __syncthreads();   // the previous unit has read lcoef and k0
-        if (tid < HT) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) lcoef[t][tid] = 0;
-        }
-        if (tid == 0) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) k0_sh[t] = k0_base;
-        }
-        __syncthreads();
-        auto add_edge = [&](int a, int b, int w) {
-            const int ia = tpos[a], ib = tpos[b];
+            };
+            if (tid < cd.n_edges) add_edge(e0a, e0b, e0w);
+            for (int e = tid + H::W; e < cd.n_edges; e += H::W)
+                add_edge(pa.e_a[cd.edge_off + e], pa.e_b[cd.edge_off + e], pa.e_w[cd.edge_off + e]);
+            __syncthreads();
+
+            // packed cut values (minus cut_min) of the thread's amplitudes in layout rotation 0
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const int xa = static_cast<int>((xo[t] >> a) & 1u), xb2 = static_cast<int>((xo[t] >> b) & 1u);
-                if (ia >= 0 && ib < 0) {
-                    atomicAdd(&lcoef[t][ia], w - 2 * w * xb2);
-                    if (xb2) atomicAdd(&k0_sh[t], w);
-                } else if (ia < 0 && ib >= 0) {
-                    atomicAdd(&lcoef[t][ib], w - 2 * w * xa);
-                    if (xa) atomicAdd(&k0_sh[t], w);
-                } else if (ia < 0 && ib < 0 && (xa ^ xb2)) {
-                    atomicAdd(&k0_sh[t], w);
+                const uint32_t qb = t ? (~htbase<CF, 0>(tau) & TBITS_0) : htbase<CF, 0>(tau);
+                int32_t lthr = k0_sh[t];
+#pragma unroll
+                for (int i = 0; i < HT; ++i)
+                    if ((qb >> i) & 1u) lthr += lcoef[t][i];
+#pragma unroll
+                for (int w2 = 0; w2 < NW; ++w2) pk[t][w2] = 0u;
+#pragma unroll
+                for (int r = 0; r < A; ++r) {
+                    const int rr = t ? A - 1 - r : r;
+                    int32_t c = lthr + ttl[qb | hroff<CF, 0>(rr)];
+#pragma unroll
+                    for (int i = 0; i < H::AB; ++i)
+                        if ((rr >> i) & 1) c += lcoef[t][i];
+                    pk[t][r >> 2] |= static_cast<uint32_t>(c) << (8 * (r & 3));
                 }
-            }
-        };
-        if (tid < cd.n_edges) add_edge(e0a, e0b, e0w);
-        for (int e = tid + H::W; e < cd.n_edges; e += H::W)
-            add_edge(pa.e_a[cd.edge_off + e], pa.e_b[cd.edge_off + e], pa.e_w[cd.edge_off + e]);
-        __syncthreads();
-
-        // packed cut values (minus cut_min) of the thread's amplitudes in layout rotation 0
-        uint32_t pk[NT][NW];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const uint32_t qb = t ? (~htbase<CF, 0>(tau) & TBITS_0) : htbase<CF, 0>(tau);
-            int32_t lthr = k0_sh[t];
-#pragma unroll
-            for (int i = 0; i < HT; ++i)
-                if ((qb >> i) & 1u) lthr += lcoef[t][i];
-#pragma unroll
-            for (int w2 = 0; w2 < NW; ++w2) pk[t][w2] = 0u;
-#pragma unroll
-            for (int r = 0; r < A; ++r) {
-                const int rr = t ? A - 1 - r : r;
-                int32_t c = lthr + ttl[qb | hroff<CF, 0>(rr)];
-#pragma unroll
-                for (int i = 0; i < H::AB; ++i)
-                    if ((rr >> i) & 1) c += lcoef[t][i];
-                pk[t][r >> 2] |= static_cast<uint32_t>(c) << (8 * (r & 3));
             }
         }
         size_t off[NT];
