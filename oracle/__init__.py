@@ -21,6 +21,7 @@ of Training QAOA", arXiv:2101.10296) step by step:
 * ``closed_form`` - the p=1 closed form of a MaxCut edge term (a published result the
                     paper relies on implicitly; used as an independent pin)
 * ``automorphisms`` - brute-force automorphism groups of tiny graphs (Sec. 2.6-2.7)
+* ``train``       - Adam ascent of the oracle energy over a batch of starting angles
 
 Every function works in float64 / complex128.  Every pin that fixes this code against
 the paper or the mathematics lives in ``tests/test_oracle_*.py``.
@@ -32,3 +33,4 @@ from .statevector import cut_values, qaoa_state, zz_expectation, zz_and_grad  # 
 from .energy import plan, energy, energy_grad, energy_fd, bruteforce_full  # noqa: F401
 from .closed_form import zz_p1  # noqa: F401
 from .automorphisms import automorphism_group, group_closure  # noqa: F401
+from .train import adam_ascent  # noqa: F401

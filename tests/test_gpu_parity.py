@@ -212,3 +212,24 @@ def test_deep_circuits(Q, p):
     check_energy(Q, g, p, ga, be, reduce=False, grad=True)
     for m in (5, 13):
         check_energy(Q, W.star(m), p, ga, be, grad=True)
+
+
+def test_adam_training_matches_oracle(Q):
+    # multi-start Adam ascent (the library's trainer against the same rule on the oracle):
+    # random 3-regular n=16 at p=2, four starts, 25 steps
+    from paper_2101_10296_amd.train import adam_ascent
+    g = W.random_regular(16, 3, 0)
+    ga, be = W.draw_angles(4, 2, 123)
+    ref = oracle.plan(g.n, g.edges, None, None, 2, reduce=False)
+    go, bo, Eo, histo = oracle.adam_ascent(ref, ga, be, steps=25, lr=0.02)
+    for graph in (False, True):
+        pl = Q.Plan(g.n, g.edges, p=2, graph=graph)
+        gg, bb, E, hist = adam_ascent(pl, dev(ga), dev(be), steps=25, lr=0.02)
+        torch.cuda.synchronize()
+        assert np.abs(gg.cpu().numpy() - go).max() <= 1e-4
+        assert np.abs(bb.cpu().numpy() - bo).max() <= 1e-4
+        assert np.abs(E.cpu().numpy() - Eo).max() <= ZZ_TOL * g.m / 2
+        assert np.abs(hist.cpu().numpy() - histo).max() <= 1e-4 * g.m
+        assert np.all(Eo > histo[0])
+        if graph:
+            assert pl.info()["graph_replays"] == 24
