@@ -229,6 +229,20 @@ def training_measure(Q, torch, W, steps: int = 20) -> dict:
                                               round(float(E.mean()) / g.m, 4)]}
 
 
+def rqaoa_measure(W) -> dict:
+    """Recursive QAOA on random 3-regular n=200 (seed 502) at p=1 with fixed angles: one plan
+    and one correlation evaluation per eliminated variable, down to 10 variables."""
+    import numpy as np
+
+    from paper_2101_10296_amd.rqaoa import rqaoa
+    g = W.random_regular(200, 3, 502)
+    t0 = time.perf_counter()
+    z, cut, steps = rqaoa(g.n, g.edges, None, 1, lambda k, n: ([0.6], [0.4]), n_stop=10)
+    dt = time.perf_counter() - t0
+    return {"workload": "random 3-regular n=200, p=1, fixed angles, down to 10 variables",
+            "steps": len(steps), "steps_per_s": round(len(steps) / dt, 1), "cut_fraction": round(cut / g.m, 4)}
+
+
 def copy_measure(torch, gib: float) -> dict:
     """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     n = int(gib * (1 << 30)) // 4
@@ -363,6 +377,10 @@ def main():
         unr.close()
         extra["graph_replay"] = replay_measure(Q, torch, W)
         extra["training"] = training_measure(Q, torch, W)
+        try:
+            extra["rqaoa"] = rqaoa_measure(W)
+        except Exception as ex:   # a contracted graph can outgrow the cone limit
+            extra["rqaoa"] = {"error": str(ex)[:200]}
 
     line = {
         "metric": "QAOA energy+grad evals/s (batched adjoint vs plain); achieved HBM GB/s",

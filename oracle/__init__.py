@@ -22,6 +22,7 @@ of Training QAOA", arXiv:2101.10296) step by step:
                     paper relies on implicitly; used as an independent pin)
 * ``automorphisms`` - brute-force automorphism groups of tiny graphs (Sec. 2.6-2.7)
 * ``train``       - Adam ascent of the oracle energy over a batch of starting angles
+* ``rqaoa``       - recursive QAOA (pair elimination) with oracle correlations
 
 Every function works in float64 / complex128.  Every pin that fixes this code against
 the paper or the mathematics lives in ``tests/test_oracle_*.py``.
@@ -34,3 +35,4 @@ from .energy import plan, energy, energy_grad, energy_fd, bruteforce_full  # noq
 from .closed_form import zz_p1  # noqa: F401
 from .automorphisms import automorphism_group, group_closure  # noqa: F401
 from .train import adam_ascent  # noqa: F401
+from . import rqaoa  # noqa: F401

@@ -233,3 +233,28 @@ def test_adam_training_matches_oracle(Q):
         assert np.all(Eo > histo[0])
         if graph:
             assert pl.info()["graph_replays"] == 24
+
+
+@pytest.mark.parametrize("case", ["ring", "torus", "rand_p1", "rand_p2"])
+def test_rqaoa_matches_oracle(Q, case):
+    # recursive QAOA: the library (GPU correlations, symmetry-reduced where generators
+    # survive) against the oracle's plain recursion (FP64, every edge its own cone): the
+    # same pairs and signs in the same order, and the same cut
+    from paper_2101_10296_amd.rqaoa import rqaoa
+    if case == "ring":
+        g, p, ang = W.circulant(12, (1,)), 1, ([np.pi / 4], [np.pi / 8])
+    elif case == "torus":
+        g, p, ang = W.torus2d(4), 1, ([0.55], [0.35])
+    elif case == "rand_p1":
+        g, p, ang = W.random_regular(14, 3, 44), 1, ([0.6], [0.4])
+    else:
+        g, p, ang = W.random_regular(14, 3, 45), 2, ([0.5, 0.8], [0.45, 0.2])
+
+    def angles(k, n):
+        return ang
+
+    z, cut, steps = rqaoa(g.n, g.edges, None, p, angles, n_stop=6, generators=g.gens())
+    zo, cuto, stepso = oracle.rqaoa.rqaoa(g.n, g.edges.tolist(), None, p, angles, n_stop=6)
+    assert [tuple(map(int, s)) for s in steps] == [tuple(map(int, s)) for s in stepso]
+    assert cut == cuto
+    assert set(z.tolist()) <= {1, -1}
