@@ -43,7 +43,7 @@ typedef int32_t qaoa_status;
 enum {
     QAOA_OK = 0,
     QAOA_EINVAL = -1,   /* bad sizes or ids, self-loop, duplicate edge, p < 1, n_points < 1,
-                           non-integer weights (the GPU path needs integer cut values) */
+                           weights without a common unit (the GPU path counts cut values in it) */
     QAOA_ENOTAUT = -2,  /* a generator is not a weight-preserving automorphism */
     QAOA_ECONE = -3,    /* a light cone exceeds max_cone_qubits, or its cut range exceeds 255 */
     QAOA_ENOMEM = -4,   /* not even one work item fits the memory budget / device memory */
@@ -63,7 +63,11 @@ typedef struct {
     int64_t n_edges;              /* |E| >= 0; the input order is the edge index */
     const int32_t* edge_u;        /* [n_edges], 0 <= id < n_nodes */
     const int32_t* edge_v;        /* [n_edges] */
-    const double* edge_w;         /* [n_edges] integer-valued weights, or NULL = unit weights */
+    const double* edge_w;         /* [n_edges] weights, or NULL = unit weights.  They must be
+                                     integer multiples of one common unit (integers, or
+                                     rationals with denominators up to 2^20 to 1e-13 relative),
+                                     at most 2^24 units
+                                     each; a cone's cut values may span at most 255 units */
     int32_t n_generators;         /* >= 0 */
     const int32_t* generators;    /* row-major [n_generators][n_nodes]: image of node i under
                                      generator g; NULL / 0 = trivial group */
@@ -102,10 +106,12 @@ typedef struct {
     int32_t min_k, max_k;         /* smallest / largest cone (qubits) */
     int64_t k_hist[31];           /* number of cones with k qubits, k = 0..30 */
     double total_weight;          /* sum of all edge weights */
-    int32_t cut_min, cut_max;     /* range of cut values over all cones */
+    int32_t cut_min, cut_max;     /* range of cut values over all cones, in weight units */
     int64_t n_hbm_cones;          /* cones too large for one workgroup (state kept in HBM) */
     int64_t device_bytes;         /* descriptor and table bytes resident on the device */
     int64_t graph_replays;        /* energy calls served by replaying a captured graph */
+    double weight_unit;           /* delta: every weight is an integer multiple of it (1 for
+                                     integer weights); cut values are counted in this unit */
 } qaoa_plan_info;
 
 void qaoa_plan_opts_default(qaoa_plan_opts* opts);

@@ -30,7 +30,7 @@ class PlanInfo(C.Structure):
                 ("min_k", C.c_int32), ("max_k", C.c_int32), ("k_hist", C.c_int64 * 31),
                 ("total_weight", C.c_double), ("cut_min", C.c_int32), ("cut_max", C.c_int32),
                 ("n_hbm_cones", C.c_int64), ("device_bytes", C.c_int64),
-                ("graph_replays", C.c_int64)]
+                ("graph_replays", C.c_int64), ("weight_unit", C.c_double)]
 
 
 _lib = None

@@ -4,13 +4,14 @@
 
 namespace qaoa {
 
-// phase[(i*p + l)*R + j] = exp(-i gamma_{i,l} c), c = cmin + j  (U_P on a basis state with
-// cut value c, Sec. 2.2 / 2.4), computed in FP64 and rounded to FP32;
+// phase[(i*p + l)*R + j] = exp(-i gamma_{i,l} delta c), c = cmin + j  (U_P on a basis state
+// whose cut is delta c, cut values counted in the plan's weight unit delta; Sec. 2.2 / 2.4,
+// weights as in Sec. 4), computed in FP64 and rounded to FP32;
 // mix[i*p + l] = (tau, |kappa|^2) of exp(-i beta_{i,l} X) = kappa X^e (1 - i tau X) (Sec. 2.2):
 // tau = tan beta, |kappa|^2 = cos^2 beta when |cos beta| >= |sin beta|, otherwise
 // tau = -cot beta, |kappa|^2 = sin^2 beta.
 __global__ void k_tables(const double* __restrict__ gamma, const double* __restrict__ beta,
-                         int64_t n_pl, int32_t R, int32_t cmin, float2* __restrict__ phase,
+                         int64_t n_pl, int32_t R, int32_t cmin, double delta, float2* __restrict__ phase,
                          float2* __restrict__ mix) {
     const int64_t total = n_pl * R;
     for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
@@ -18,7 +19,7 @@ __global__ void k_tables(const double* __restrict__ gamma, const double* __restr
         const int64_t pl = t / R;
         const int32_t j = static_cast<int32_t>(t - pl * R);
         double s, c;
-        sincos(gamma[pl] * static_cast<double>(cmin + j), &s, &c);
+        sincos(gamma[pl] * delta * static_cast<double>(cmin + j), &s, &c);
         phase[t] = make_float2(static_cast<float>(c), static_cast<float>(-s));
         if (j == 0) {
             // exp(-i beta X) = kappa X^e (1 - i tau X): the bounded factorisation
@@ -60,7 +61,7 @@ __global__ void k_cut_tables(const ConeDev* __restrict__ cones, const int32_t* _
 // Fixed-order reduction (deterministic): thread t sums m = t, t + 256, ...; then a tree.
 __global__ void __launch_bounds__(256)
 k_combine(const double* __restrict__ W, const double* __restrict__ zz, const double* __restrict__ g,
-          int32_t M, int32_t p, double* __restrict__ energy, double* __restrict__ dgamma,
+          int32_t M, int32_t p, double delta, double* __restrict__ energy, double* __restrict__ dgamma,
           double* __restrict__ dbeta) {
     __shared__ double sh[256];
     const int i = blockIdx.x;
@@ -79,18 +80,18 @@ k_combine(const double* __restrict__ W, const double* __restrict__ zz, const dou
     }
     if (threadIdx.x == 0) {
         if (y == 0) energy[i] = sh[0];
-        else if (y - 1 < p) dgamma[static_cast<size_t>(i) * p + (y - 1)] = sh[0];
+        else if (y - 1 < p) dgamma[static_cast<size_t>(i) * p + (y - 1)] = delta * sh[0];   // C in units of delta
         else dbeta[static_cast<size_t>(i) * p + (y - 1 - p)] = sh[0];
     }
 }
 
 hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, int32_t R, int32_t cmin,
-                         float2* phase, float2* mix, hipStream_t st) {
+                         double delta, float2* phase, float2* mix, hipStream_t st) {
     const int64_t total = n_pl * R;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_tables, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, gamma, beta, n_pl, R,
-                       cmin, phase, mix);
+                       cmin, delta, phase, mix);
     return hipGetLastError();
 }
 
@@ -103,10 +104,10 @@ hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_
 }
 
 hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
-                          double* energy, double* dgamma, double* dbeta, hipStream_t st) {
+                          double delta, double* energy, double* dgamma, double* dbeta, hipStream_t st) {
     const unsigned ny = (g != nullptr) ? static_cast<unsigned>(1 + 2 * p) : 1u;
-    hipLaunchKernelGGL(k_combine, dim3(static_cast<unsigned>(P), ny), dim3(256), 0, st, W, zz, g, M, p, energy,
-                       dgamma, dbeta);
+    hipLaunchKernelGGL(k_combine, dim3(static_cast<unsigned>(P), ny), dim3(256), 0, st, W, zz, g, M, p, delta,
+                       energy, dgamma, dbeta);
     return hipGetLastError();
 }
 

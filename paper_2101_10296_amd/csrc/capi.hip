@@ -94,6 +94,7 @@ qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
     out->cut_max = hp.cut_max;
     out->device_bytes = static_cast<int64_t>(plan->resident_bytes);
     out->graph_replays = plan->graph_replays;
+    out->weight_unit = plan->hp.delta;
     return QAOA_OK;
 }
 

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 
 namespace qaoa {
 namespace {
@@ -63,6 +64,65 @@ struct MinUnionFind {
     }
 };
 
+// Smallest denominator q <= qmax with |x - a/q| <= tol (continued-fraction convergents),
+// or 0 if there is none.
+int64_t rational_denominator(double x, int64_t qmax, double tol) {
+    double r = std::fabs(x);
+    int64_t h0 = 0, h1 = 1, k0 = 1, k1 = 0;   // convergents h/k
+    for (int it = 0; it < 64; ++it) {
+        const double a = std::floor(r);
+        if (a > 9.0e15) break;
+        const int64_t ai = static_cast<int64_t>(a);
+        const int64_t h2 = ai * h1 + h0, k2 = ai * k1 + k0;
+        if (k2 > qmax) break;
+        h0 = h1; h1 = h2; k0 = k1; k1 = k2;
+        if (std::fabs(std::fabs(x) - static_cast<double>(h1) / static_cast<double>(k1)) <= tol) return k1;
+        const double frac = r - a;
+        if (frac <= 0.0) break;
+        r = 1.0 / frac;
+    }
+    return 0;
+}
+
+// Weights become integers wi in units of delta (w = delta * wi): the kernels keep cut
+// values as small integers.  Integer weights use delta = 1; otherwise every weight must be
+// a rational with a denominator of at most 2^20 (to 1e-13 relative), delta = g / L with L
+// the least common denominator and g the gcd of the scaled weights.
+void weight_units(HostPlan& P) {
+    const int64_t m = static_cast<int64_t>(P.w.size());
+    P.wi.assign(m, 1);
+    P.delta = 1.0;
+    bool integral = true;
+    for (double x : P.w) integral = integral && x == std::floor(x) && std::fabs(x) <= 16777216.0;
+    if (integral) {
+        for (int64_t i = 0; i < m; ++i) P.wi[i] = static_cast<int32_t>(P.w[i]);
+        return;
+    }
+    int64_t L = 1;
+    for (int64_t i = 0; i < m; ++i) {
+        const double x = P.w[i];
+        const int64_t q = rational_denominator(x, int64_t{1} << 20, 1e-13 * std::max(1.0, std::fabs(x)));
+        if (q == 0)
+            fail(kEINVAL, "edge " + std::to_string(i) + ": weight is not a rational with a denominator of at most 2^20");
+        L = L / std::gcd(L, q) * q;
+        if (L > (int64_t{1} << 40)) fail(kEINVAL, "weights have no common unit (denominators too large)");
+    }
+    std::vector<int64_t> n(m);
+    int64_t g = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        n[i] = std::llround(P.w[i] * static_cast<double>(L));
+        g = std::gcd(g, std::llabs(n[i]));
+    }
+    if (g == 0) g = 1;
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t v = n[i] / g;
+        if (std::llabs(v) > (int64_t{1} << 24))
+            fail(kEINVAL, "edge " + std::to_string(i) + ": weight is more than 2^24 units of the common weight unit");
+        P.wi[i] = static_cast<int32_t>(v);
+    }
+    P.delta = static_cast<double>(g) / static_cast<double>(L);
+}
+
 }  // namespace
 
 void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* ew,
@@ -94,12 +154,11 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
         if (ew) {
             const double x = ew[i];
             if (!std::isfinite(x)) fail(kEINVAL, "edge " + std::to_string(i) + ": non-finite weight");
-            if (x != std::floor(x) || std::fabs(x) > 16777216.0)
-                fail(kEINVAL, "edge " + std::to_string(i) + ": weights must be integers of magnitude <= 2^24");
             P.w[i] = x;
             if (x != 1.0) P.unit = false;
         }
     }
+    weight_units(P);
     EdgeIndex index;
     index.build(n, P.u, P.v);
     for (int64_t i = 1; i < m; ++i)
@@ -200,7 +259,7 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
                 if (mark[y] == stamp && loc[y] > i) {
                     c.ea.push_back(i);
                     c.eb.push_back(loc[y]);
-                    const int32_t wi = static_cast<int32_t>(P.w[nbr_e[j]]);
+                    const int32_t wi = P.wi[nbr_e[j]];
                     c.ew.push_back(wi);
                     if (wi < 0) cmin += wi; else cmax += wi;
                 }

@@ -27,6 +27,8 @@ struct HostPlan {
     int64_t m = 0;
     std::vector<int32_t> u, v;             // canonical edges, u < v, input order
     std::vector<double> w;                 // weights (1.0 when unit)
+    std::vector<int32_t> wi;               // weights in units of delta (integers)
+    double delta = 1.0;                    // weight unit: w = delta * wi exactly
     bool unit = true;
     std::vector<int32_t> edge_orbit;       // [m]
     std::vector<int64_t> rep, size;        // [M]

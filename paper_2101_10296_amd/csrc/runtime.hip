@@ -309,7 +309,8 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
     }
     GroupTimer tm(P, stream);
     QCHECK(tm.begin(-1, static_cast<int64_t>(npl)));
-    QCHECK(launch_tables(gamma, beta, static_cast<int64_t>(npl), R, hp.cut_min, P->d_phase, P->d_mix, stream));
+    QCHECK(launch_tables(gamma, beta, static_cast<int64_t>(npl), R, hp.cut_min, hp.delta, P->d_phase, P->d_mix,
+                         stream));
     QCHECK(tm.end());
     EvalArgs ea{static_cast<int32_t>(n_points), p, M, R, P->d_phase, P->d_mix, zz, g};
     for (const auto& grp : P->lds_groups) {
@@ -412,7 +413,7 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         QCHECK(tm.end());
     }
     QCHECK(tm.begin(-2, n_points));
-    QCHECK(launch_combine(P->d_W, zz, g, M, p, n_points, energy, dgamma, dbeta, stream));
+    QCHECK(launch_combine(P->d_W, zz, g, M, p, n_points, hp.delta, energy, dgamma, dbeta, stream));
     QCHECK(tm.end());
     return QAOA_OK;
 }

@@ -94,7 +94,7 @@ qaoa_status kernel_times(qaoa_plan_s* plan, int32_t cap, int32_t* k_out, int64_t
 hipError_t launch_fused(int K, bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
                         const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st);
 hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, int32_t R, int32_t cmin,
-                         float2* phase, float2* mix, hipStream_t st);
+                         double delta, float2* phase, float2* mix, hipStream_t st);
 hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
                              const int32_t* ew, uint8_t* tables, hipStream_t st);
 hipError_t launch_pass(int kind, const PassArgs& pa, hipStream_t st);
@@ -114,6 +114,6 @@ int hbm_group_qubits(int k, int grp);
 std::vector<PassSpec> hbm_program(int k, int p, bool grad);
 
 hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
-                          double* energy, double* dgamma, double* dbeta, hipStream_t st);
+                          double delta, double* energy, double* dgamma, double* dbeta, hipStream_t st);
 
 }  // namespace qaoa

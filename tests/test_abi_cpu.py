@@ -101,7 +101,8 @@ def test_weighted_planner_and_weight_preservation():
     (dict(edges=[[0, 1], [1, 0]], n=3), Q.QAOA_EINVAL),
     (dict(edges=[[0, 5]], n=3), Q.QAOA_EINVAL),
     (dict(edges=[[0, 1]], n=3, p=0), Q.QAOA_EINVAL),
-    (dict(edges=[[0, 1]], n=3, weights=[0.5]), Q.QAOA_EINVAL),
+    (dict(edges=[[0, 1], [1, 2]], n=3, weights=[1.0, 2 ** 0.5]), Q.QAOA_EINVAL),
+    (dict(edges=[[0, 1], [1, 2]], n=3, weights=[1.0, float("nan")]), Q.QAOA_EINVAL),
     (dict(edges=[[0, 1], [1, 2]], n=3, generators=[[1, 0, 2]]), Q.QAOA_ENOTAUT),
     (dict(edges=[[0, 1], [1, 2]], n=3, generators=[[0, 0, 2]]), Q.QAOA_ENOTAUT),
     (dict(edges=W.complete(40).edges, n=40), Q.QAOA_ECONE),
@@ -121,6 +122,17 @@ def test_option_errors(opts):
     with pytest.raises(Q.QaoaError) as ei:
         Q.Plan(3, [[0, 1], [1, 2]], p=1, **opts)
     assert ei.value.status == Q.QAOA_EINVAL
+
+
+@pytest.mark.parametrize("w,unit", [([1.0, 2.0, 3.0], 1.0), ([0.5, 1.5, 1.0], 0.5), ([0.1, 0.3, 0.2], 0.1),
+                                    ([0.25, -0.75, 1.0], 0.25), ([1 / 3, 2 / 3, 1.0], 1 / 3), ([2.0, 4.0, 6.0], 1.0)])
+def test_weight_unit(w, unit):
+    # weights are counted in their common unit: the largest delta with every w / delta an
+    # integer (integer weights keep delta = 1)
+    pl = Q.Plan(4, [[0, 1], [1, 2], [2, 3]], p=1, weights=w)
+    info = pl.info()
+    assert abs(info["weight_unit"] - unit) <= 1e-15 * max(1.0, unit)
+    assert info["total_weight"] == pytest.approx(sum(w), rel=1e-15, abs=1e-15)
 
 
 def test_cut_range_limit():

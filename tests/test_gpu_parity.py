@@ -258,3 +258,27 @@ def test_rqaoa_matches_oracle(Q, case):
     assert [tuple(map(int, s)) for s in steps] == [tuple(map(int, s)) for s in stepso]
     assert cut == cuto
     assert set(z.tolist()) <= {1, -1}
+
+
+def test_rational_weights(Q):
+    # weights with a common unit other than 1 (cut values counted in that unit): 1/2 and
+    # signed quarters, unreduced, energy and gradient against the oracle
+    g = W.random_regular(14, 3, 9)
+    rng = np.random.default_rng(3)
+    ga, be = W.draw_angles(4, 2, 31)
+    for choices, unit in (([0.5, 1.0, 1.5], 0.5), ([-0.25, 0.75, 0.5], 0.25)):
+        w = rng.choice(choices, size=g.m)
+        pl, _, _ = check_energy(Q, g, 2, ga, be, reduce=False, weights=w, grad=True)
+        assert pl.info()["weight_unit"] == unit
+
+
+def test_rational_weights_with_symmetry(Q):
+    # C_40(1,2) with weight 1/2 on the step-1 edges and 5/4 on the step-2 edges: the
+    # rotation and reflection preserve the weights, two orbits
+    g = W.circulant(40, (1, 2))
+    d = (g.edges[:, 1] - g.edges[:, 0]) % g.n
+    step = np.minimum(d, g.n - d)
+    w = np.where(step == 1, 0.5, 1.25)
+    ga, be = W.draw_angles(3, 2, 32)
+    pl, _, _ = check_energy(Q, g, 2, ga, be, reduce=True, weights=w, grad=True)
+    assert pl.info()["n_orbits"] == 2 and pl.info()["weight_unit"] == 0.25
