@@ -229,6 +229,22 @@ def training_measure(Q, torch, W, steps: int = 20) -> dict:
                                               round(float(E.mean()) / g.m, 4)]}
 
 
+def generator_measure(Q, W) -> dict:
+    """Automorphism generators found by the library's search (host) for the 100 x 100 torus,
+    the paper's grid-w-2-100 row, and the edge orbits they give."""
+    import numpy as np
+    g = W.torus2d(100)
+    t0 = time.perf_counter()
+    gens, complete = Q.find_generators(g.n, g.edges)
+    dt = time.perf_counter() - t0
+    pl = Q.Plan(g.n, g.edges, p=1, generators=gens)
+    n_orb = pl.info()["n_orbits"]
+    pl.close()
+    return {"graph": "torus 100x100 (10000 nodes, 20000 edges)", "seconds": round(dt, 3),
+            "generators": int(len(gens)), "complete": bool(complete), "edge_orbits": int(n_orb),
+            "paper_t_aut_s_context": 58.70}
+
+
 def rqaoa_measure(W) -> dict:
     """Recursive QAOA on random 3-regular n=200 (seed 502) at p=1 with fixed angles: one plan
     and one correlation evaluation per eliminated variable, down to 10 variables."""
@@ -377,6 +393,7 @@ def main():
         unr.close()
         extra["graph_replay"] = replay_measure(Q, torch, W)
         extra["training"] = training_measure(Q, torch, W)
+        extra["generator_search"] = generator_measure(Q, W)
         try:
             extra["rqaoa"] = rqaoa_measure(W)
         except Exception as ex:   # a contracted graph can outgrow the cone limit

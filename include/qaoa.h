@@ -165,6 +165,22 @@ qaoa_status qaoa_plan_kernel_times(qaoa_plan_t plan, int32_t cap, int32_t* k_out
                                    double* ms_out, int32_t* n_out);
 
 /* Release the plan and everything it owns on the device (synchronises the device). */
+/* Automorphism generators of the problem's graph (edge weights act as edge colours), for
+ * graphs whose symmetry group is not known by construction; the paper obtains its group
+ * from an automorphism solver (Sec. 2.6, Sec. 5).  Colour refinement and
+ * individualisation; every permutation written is a verified weight-preserving automorphism
+ * and can be passed as problem->generators.
+ *   pr->n_nodes, n_edges, edge_u, edge_v, edge_w are read; generators and p are ignored.
+ *   max_generators   capacity of `generators`
+ *   time_limit_s     wall-clock limit of the search (> 0)
+ *   generators       HOST [max_generators][n_nodes], caller-owned: image of node i under g
+ *   n_found          number of generators written
+ *   complete         1 if the search finished (the generators generate the automorphism
+ *                    group), 0 if a limit ended it (they generate a subgroup)
+ * Errors: QAOA_EINVAL for a bad graph (ids, self-loops, duplicate edges) or limits. */
+qaoa_status qaoa_find_generators(const qaoa_problem* pr, int32_t max_generators, double time_limit_s,
+                                 int32_t* generators, int32_t* n_found, int32_t* complete);
+
 void qaoa_plan_destroy(qaoa_plan_t plan);
 
 /* Text of the last failure on this thread ("" if none). */

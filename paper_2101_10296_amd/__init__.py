@@ -189,6 +189,31 @@ class Plan:
             pass
 
 
+def find_generators(n_nodes: int, edges, weights=None, max_generators: int = 256, time_limit: float = 30.0):
+    """Automorphism generators of a graph whose symmetry is not known (edge weights act as
+    colours): (generators int32 [g, n], complete).  Every row is a verified automorphism;
+    complete is False when the time limit or the capacity ended the search (the rows then
+    generate a subgroup, which the orbit reduction accepts)."""
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    u, v = _i32(e[:, 0]), _i32(e[:, 1])
+    w = None if weights is None else np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+    pr = _capi.Problem()
+    pr.n_nodes = int(n_nodes)
+    pr.n_edges = int(e.shape[0])
+    pr.edge_u = u.ctypes.data_as(C.POINTER(C.c_int32))
+    pr.edge_v = v.ctypes.data_as(C.POINTER(C.c_int32))
+    pr.edge_w = None if w is None else w.ctypes.data_as(C.POINTER(C.c_double))
+    pr.n_generators = 0
+    pr.generators = None
+    pr.p = 1
+    out = np.zeros((int(max_generators), int(n_nodes)), np.int32)
+    nf = C.c_int32()
+    done = C.c_int32()
+    _check(_capi.lib().qaoa_find_generators(C.byref(pr), int(max_generators), float(time_limit),
+                                            out.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nf), C.byref(done)))
+    return out[: nf.value].copy(), bool(done.value)
+
+
 def _autograd_fn():
     import torch
 

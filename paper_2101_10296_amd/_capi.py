@@ -61,6 +61,9 @@ def lib():
         L.qaoa_plan_kernel_times.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double),
                                              C.POINTER(i32)]
         L.qaoa_plan_kernel_times.restype = i32
+        L.qaoa_find_generators.argtypes = [C.POINTER(Problem), i32, C.c_double, C.POINTER(i32), C.POINTER(i32),
+                                           C.POINTER(i32)]
+        L.qaoa_find_generators.restype = i32
         L.qaoa_plan_destroy.argtypes = [vp]
         L.qaoa_plan_destroy.restype = None
         L.qaoa_last_error.argtypes = []

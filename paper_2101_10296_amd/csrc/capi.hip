@@ -32,6 +32,30 @@ void qaoa_plan_opts_default(qaoa_plan_opts* o) {
 
 const char* qaoa_last_error(void) { return g_last_error.c_str(); }
 
+qaoa_status qaoa_find_generators(const qaoa_problem* pr, int32_t max_generators, double time_limit_s,
+                                 int32_t* generators, int32_t* n_found, int32_t* complete) {
+    if (!pr || !n_found || !complete || (max_generators > 0 && !generators))
+        return set_err(QAOA_EINVAL, "NULL argument");
+    if (max_generators < 0 || !(time_limit_s > 0.0)) return set_err(QAOA_EINVAL, "bad limits");
+    try {
+        std::vector<std::vector<int32_t>> gens;
+        bool done = false;
+        std::string msg;
+        const int64_t leaf_budget = int64_t{1} << 20;
+        if (qaoa::find_generators(pr->n_nodes, pr->n_edges, pr->edge_u, pr->edge_v, pr->edge_w, max_generators,
+                                  time_limit_s, leaf_budget, gens, done, msg) != 0)
+            return set_err(QAOA_EINVAL, msg);
+        for (size_t g = 0; g < gens.size(); ++g)
+            std::memcpy(generators + g * static_cast<size_t>(pr->n_nodes), gens[g].data(),
+                        sizeof(int32_t) * static_cast<size_t>(pr->n_nodes));
+        *n_found = static_cast<int32_t>(gens.size());
+        *complete = done ? 1 : 0;
+        return QAOA_OK;
+    } catch (const std::bad_alloc&) {
+        return set_err(QAOA_ENOMEM, "host allocation failed");
+    }
+}
+
 qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* opts, qaoa_plan_t* out) {
     if (!pr || !out) return set_err(QAOA_EINVAL, "problem or out is NULL");
     *out = nullptr;

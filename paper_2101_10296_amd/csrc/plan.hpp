@@ -54,4 +54,10 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
                      int32_t n_gen, const int32_t* gens, int32_t p, const PlanOptions& opt,
                      HostPlan& out);
 
+// Automorphism generators of a weighted graph by individualisation and refinement
+// (autgen.cpp).  Returns 0, or -1 with msg on bad input.
+int32_t find_generators(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* ew, int32_t max_gens,
+                        double seconds, int64_t leaf_budget, std::vector<std::vector<int32_t>>& gens, bool& complete,
+                        std::string& msg);
+
 }  // namespace qaoa
