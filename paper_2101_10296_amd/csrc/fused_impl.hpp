@@ -474,7 +474,7 @@ __device__ __forceinline__ double item_sum(double x, double* red, int tid) {
 // layer p-1 ends in stage 0 (qubits 0 and 1).  With ODD the first layer is descending and
 // is peeled off; the remaining layers come in (ascending, descending) pairs, so no branch
 // ever selects between the two layer bodies.
-template <int K, bool GRAD, bool ODD, bool DB>
+template <int K, bool GRAD, bool ODD, bool DB, bool GR>
 __global__ void __launch_bounds__((Fz<(K >= 3 ? K - 1 : K), (GRAD ? 1 : 0)>::WG))
 k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         const uint8_t* __restrict__ cut_tables, int32_t rowcap, EvalArgs ea) {
@@ -519,14 +519,18 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     float2* xb2 = DB ? xbuf + (C::S > 1 ? (C::IPW + il) * C::NPAD : 0) : nullptr;
     const float2* phase0 = ea.phase + static_cast<size_t>(point) * p * ea.R + cd.cut_shift;
     const float2* mix0 = ea.mix + static_cast<size_t>(point) * p;
-    {   // phase rows of every layer for this item: prow[il][l][c] = exp(-i gamma_l (cut_min + c))
+    // phase rows of every layer for this item: prow[il][l][c] = exp(-i gamma_l (cut_min + c)),
+    // staged in LDS; GR: they do not fit beside the kernel's LDS (deep circuits with many
+    // items per workgroup) and are read from the table in device memory instead
+    if constexpr (!GR) {
         float2* dst = prow_all + static_cast<size_t>(il) * p * rowcap;
         for (int l = 0; l < p; ++l)
             for (int c = static_cast<int>(tau); c < cd.cut_range; c += C::TPI)
                 dst[l * rowcap + c] = phase0[static_cast<size_t>(l) * ea.R + c];
     }
-    const float2* rows = prow_all + static_cast<size_t>(il) * p * rowcap;
-    auto ROW = [&](int l) { return rows + l * rowcap; };
+    const float2* rows = GR ? phase0 : prow_all + static_cast<size_t>(il) * p * rowcap;
+    const int rstride = GR ? ea.R : rowcap;
+    auto ROW = [&](int l) { return rows + l * rstride; };
     constexpr int SL = C::S - 1;
     constexpr int NW = (A + 3) / 4;
     __syncthreads();
@@ -654,6 +658,46 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
 }
 
 // ---------------------------------------------------------------- launcher
+// LDS bytes a kernel variant declares statically (queried once per variant)
+template <int K, bool GRAD, bool ODD, bool DB, bool GR>
+hipError_t static_lds(size_t& out) {
+    static size_t bytes = 0;   // + 1 once queried
+    if (!bytes) {
+        hipFuncAttributes fa{};
+        const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, GRAD, ODD, DB, GR>));
+        if (e != hipSuccess) return e;
+        bytes = fa.sharedSizeBytes + 1;
+    }
+    out = bytes - 1;
+    return hipSuccess;
+}
+
+// Picks the variant whose LDS holds the phase rows (dyn bytes): two transpose buffers
+// (adjoint, 13 and 14 qubits) when they fit, else one, else rows stay in device memory.
+template <int K, bool GRAD, bool ODD>
+hipError_t launch_v(dim3 grid, dim3 block, size_t dyn, const ConeDev* cones, int64_t item_base, int64_t n_items,
+                    const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
+    constexpr size_t LDS_MAX = 160 * 1024;
+    size_t lds = 0;
+    hipError_t e;
+    if constexpr (GRAD && K >= 13) {
+        if ((e = static_lds<K, GRAD, ODD, true, false>(lds)) != hipSuccess) return e;
+        if (lds + dyn <= LDS_MAX) {
+            hipLaunchKernelGGL((k_fused<K, GRAD, ODD, true, false>), grid, block, dyn, st, cones, item_base, n_items,
+                               cut, rowcap, ea);
+            return hipGetLastError();
+        }
+    }
+    if ((e = static_lds<K, GRAD, ODD, false, false>(lds)) != hipSuccess) return e;
+    if (lds + dyn <= LDS_MAX)
+        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, false>), grid, block, dyn, st, cones, item_base, n_items,
+                           cut, rowcap, ea);
+    else
+        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, true>), grid, block, 0, st, cones, item_base, n_items, cut,
+                           -1, ea);
+    return hipGetLastError();
+}
+
 template <int K>
 hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
                            const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
@@ -666,36 +710,11 @@ hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t 
     const size_t dyn = static_cast<size_t>(ipw) * ea.p * rowcap * sizeof(float2);
     const dim3 grid(static_cast<unsigned>(blocks)), block(wg);
     const bool odd = ((ea.p - 1) & 1) != 0;
-    if (grad) {
-        if constexpr (K >= 13) {
-            // two LDS buffers when the phase rows still fit beside them
-            static size_t db_static[2] = {0, 0};
-            const int oi = odd ? 1 : 0;
-            if (!db_static[oi]) {
-                hipFuncAttributes fa{};
-                const hipError_t e = odd ? hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, true, true, true>))
-                                         : hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, true, false, true>));
-                if (e != hipSuccess) return e;
-                db_static[oi] = fa.sharedSizeBytes;
-            }
-            if (db_static[oi] + dyn <= 160 * 1024) {
-                if (odd)
-                    hipLaunchKernelGGL((k_fused<K, true, true, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-                else
-                    hipLaunchKernelGGL((k_fused<K, true, false, true>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-                return hipGetLastError();
-            }
-        }
-        if (odd)
-            hipLaunchKernelGGL((k_fused<K, true, true, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-        else
-            hipLaunchKernelGGL((k_fused<K, true, false, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-    } else if (odd) {
-        hipLaunchKernelGGL((k_fused<K, false, true, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-    } else {
-        hipLaunchKernelGGL((k_fused<K, false, false, false>), grid, block, dyn, st, cones, item_base, n_items, cut, rowcap, ea);
-    }
-    return hipGetLastError();
+    if (grad)
+        return odd ? launch_v<K, true, true>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st)
+                   : launch_v<K, true, false>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st);
+    return odd ? launch_v<K, false, true>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st)
+               : launch_v<K, false, false>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st);
 }
 
 }  // namespace qaoa

@@ -75,9 +75,9 @@ static hipError_t launch_one(const PassArgs& pa, hipStream_t st) {
     const int64_t units = CF >= 2 ? tiles / 2 : tiles;   // tile pairs on group 0
     if (pa.tpw < 1 || units % pa.tpw != 0) return hipErrorInvalidValue;
     const int64_t blocks = units * pa.n_batch / pa.tpw;
-    const size_t dyn = static_cast<size_t>(pa.ea.p) * pa.rowcap * sizeof(float2);
+    const size_t dyn = 3 * static_cast<size_t>(pa.rowcap) * sizeof(float2);   // three phase rows
     if constexpr (CF == 3) {
-        // two LDS buffers when the phase rows still fit beside them
+        // two LDS buffers when they fit beside the phase rows
         static size_t db_static = 0;
         if (!db_static) {
             hipFuncAttributes fa{};

@@ -331,7 +331,7 @@ k_pass(PassArgs pa) {
     __shared__ double red[H::W / 64];
     __shared__ int32_t k0_sh[NT];
     __shared__ int8_t tpos[32];          // tile bit of each global bit, -1 outside the tile
-    extern __shared__ float2 rows[];   // [p][rowcap]
+    extern __shared__ float2 rows[];   // [3][rowcap]
 
     const int tid = threadIdx.x;
     const uint32_t tau = static_cast<uint32_t>(tid);
@@ -354,14 +354,20 @@ k_pass(PassArgs pa) {
     const uint32_t pm = (pa.group == 0) ? (HN - 1u) : ((1u << h) - 1u);
     const int32_t k0_base = pa.cones[cslot].tt_min[pa.group] - cd.cut_min;
     if (CUTS && tid < 32) tpos[tid] = -1;
+    // the phase rows a pass reads -> LDS: [0] layer 1, [1] layer lb, [2] layer p
+    const float2* ph0 = pa.ea.phase + static_cast<size_t>(point) * p * pa.ea.R + cd.cut_shift;
+    const float2* row_first = rows;
+    const float2* row_lb = rows + pa.rowcap;
+    const float2* row_last = rows + 2 * pa.rowcap;
     if constexpr (CUTS) {
         const uint8_t* src = pa.tt + pa.cones[cslot].tt_off[pa.group];
         for (uint32_t q = tau * 16; q < HN; q += H::W * 16)
             *reinterpret_cast<uint4*>(ttl + q) = *reinterpret_cast<const uint4*>(src + q);
-        const float2* ph0 = pa.ea.phase + static_cast<size_t>(point) * p * pa.ea.R + cd.cut_shift;
-        for (int l = 0; l < p; ++l)
+        const int lsel[3] = {0, pa.lb > 0 ? pa.lb - 1 : 0, p - 1};
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
             for (int c = tid; c < cd.cut_range; c += H::W)
-                rows[l * pa.rowcap + c] = ph0[static_cast<size_t>(l) * pa.ea.R + c];
+                rows[s * pa.rowcap + c] = ph0[static_cast<size_t>(lsel[s]) * pa.ea.R + c];
     }
     __syncthreads();
     if (CUTS && tid < HT) {
@@ -530,7 +536,7 @@ k_pass(PassArgs pa) {
         // ------------------------------------------------------------ forward part
         if constexpr (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) gen_stage(f[t], pk[t], rows, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
+            for (int t = 0; t < NT; ++t) gen_stage(f[t], pk[t], row_first, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
             if constexpr (KIND == FWD_GEN_MIX) {
                 const float t1 = mix0[0].x;
 #pragma unroll
@@ -561,7 +567,7 @@ k_pass(PassArgs pa) {
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                phase_stage(f[t], pk[t], rows + (pa.lb - 1) * pa.rowcap, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
+                phase_stage(f[t], pk[t], row_lb, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
             if constexpr (KIND == FWD_BND_MIX) {
                 const float tb = mix0[pa.lb - 1].x;
 #pragma unroll
@@ -620,13 +626,13 @@ k_pass(PassArgs pa) {
                 if constexpr (KIND == GR_GEN_FINAL) {
                     float a = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], rows, cd.cut_min, 1.f);
+                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
                     part[2] += 2.0 * static_cast<double>(mu) * mu * a;
                 } else {
                     float a = 0.f;
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
-                        a += cgrad_stage<true>(f[t], lm[t], pk[t], rows + (p - 1) * pa.rowcap, cd.cut_min, mu);
+                        a += cgrad_stage<true>(f[t], lm[t], pk[t], row_last, cd.cut_min, mu);
                     part[2] += 2.0 * static_cast<double>(mu) * mu * a;
                     // undo mixer la = p-1 on this group (state sits in rotation 0)
                     const float2 tka = mix0[pa.la - 1];
@@ -706,13 +712,13 @@ k_pass(PassArgs pa) {
                 if constexpr (KIND == RV_GEN_MIX) {
                     float a = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], rows, cd.cut_min, 1.f);
+                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
                     part[1] += 2.0 * static_cast<double>(mu) * mu * a;
                 } else {
                     float a = 0.f;
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
-                        a += cgrad_stage<true>(f[t], lm[t], pk[t], rows + (pa.lb - 1) * pa.rowcap, cd.cut_min, mu);
+                        a += cgrad_stage<true>(f[t], lm[t], pk[t], row_lb, cd.cut_min, mu);
                     part[1] += 2.0 * static_cast<double>(mu) * mu * a;
                     const float2 tka = mix0[pa.la - 1];
                     const float wa0 = exp2f(pa.m0a * log2f(tka.y));

@@ -141,3 +141,12 @@ def test_deep_circuits_device_memory(Q, p):
     ga, be = W.draw_angles(2, p, 80 + p)
     for m in (14, 15):
         check_energy(Q, W.star(m), p, ga, be, grad=True)
+
+
+def test_deep_weighted_star_rows_in_device_memory(Q):
+    # a 15-qubit cone (device-memory passes) with weight 17 on each of its 14 edges: cut
+    # range 239, so p = 45 phase rows (86 KB) do not fit beside the pass kernels' LDS
+    g = W.star(14)
+    w = np.full(g.m, 17.0)
+    ga, be = W.draw_angles(2, 45, 93)
+    check_energy(Q, g, 45, ga, be, weights=w)

@@ -282,3 +282,12 @@ def test_rational_weights_with_symmetry(Q):
     ga, be = W.draw_angles(3, 2, 32)
     pl, _, _ = check_energy(Q, g, 2, ga, be, reduce=True, weights=w, grad=True)
     assert pl.info()["n_orbits"] == 2 and pl.info()["weight_unit"] == 0.25
+
+
+def test_deep_circuits_phase_rows_in_device_memory(Q):
+    # phase rows of 64 two- and three-qubit items per workgroup at p = 150 / 120 do not fit
+    # in LDS: the kernels read them from the table in device memory instead
+    ga, be = W.draw_angles(2, 150, 91)
+    check_energy(Q, W.single_edge(), 150, ga, be, grad=True)
+    ga, be = W.draw_angles(2, 120, 92)
+    check_energy(Q, W.triangle(), 120, ga, be, grad=True)
