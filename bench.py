@@ -29,13 +29,13 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "e00c16f4e9a8b42acdcf264bfc01026b36637bab8bb29b8d0909c011e3852d7c",
-               "counted_over_algorithmic": 1.022}
+HBM_TRAFFIC = {"sources_sha256": "e7e0869c6f34276dc342346b225693e043995ff88628920adbaac05ec45ecb87",
+               "counted_over_algorithmic": 1.018}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
 # item (cut tables and phase rows read, five FP64 results written).
-FUSED_TRAFFIC = {"sources_sha256": "babb4f6b363e102a65d33f4109ddd6c5644877aa21b3f82187f4dba063a5dff1",
+FUSED_TRAFFIC = {"sources_sha256": "eaa44ab50f60a92dad8eb84266d46a602a1567555d530909f8cfcd76c74d2409",
                  "bytes_per_item": 297.5}
 
 
