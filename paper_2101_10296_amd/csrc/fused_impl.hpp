@@ -48,7 +48,10 @@ struct Fz {
     static constexpr int TPI = 1 << TB;            // threads per item
     static constexpr int WG = TPI > 64 ? TPI : 64;
     static constexpr int IPW = WG / TPI;           // items per workgroup
-    static constexpr int S = (K + AB - 1) / AB;    // stages
+    // LQ: K = S * AB + 1, so the one qubit left over (K-1) sits on lane bit 0 in the last
+    // stage and is mixed across lanes there instead of costing a stage of its own.
+    static constexpr bool LQ = K % AB == 1 && K / AB >= 2;
+    static constexpr int S = LQ ? K / AB : (K + AB - 1) / AB;   // stages
     static constexpr uint32_t N = 1u << K;
     static constexpr uint32_t NPAD = N + (N >> 5) + (N >> 10);  // padded LDS item buffer
 };
@@ -118,9 +121,25 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
     return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
 }
 
+// The same amplitude in the neighbouring lane (lane xor 1): DPP quad_perm [1, 0, 3, 2].
+__device__ __forceinline__ float2 lane_x1(float2 v) {
+    return make_float2(__int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.x), 0xB1, 0xF, 0xF, true)),
+                       __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.y), 0xB1, 0xF, 0xF, true)));
+}
+
 template <int K, int G, int ST, int A>
 __device__ __forceinline__ void mix_stage(float2 (&v)[A], float t) {
     constexpr int AB = Fz<K, G>::AB;
+    if constexpr (Fz<K, G>::LQ && ST == Fz<K, G>::S - 1) {
+        // qubit K-1 on lane bit 0: the butterfly partner is the neighbouring lane
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 q = lane_x1(v[r]);
+            v[r] = make_float2(fmaf(t, q.y, v[r].x), fmaf(-t, q.x, v[r].y));
+            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
         if (ST * AB + i >= K) continue;  // wrapped bit: handled in stage 0
@@ -143,6 +162,23 @@ template <int K, int G, int ST, int A>
 __device__ __forceinline__ float unmix_stage2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w) {
     constexpr int AB = Fz<K, G>::AB;
     float acc = 0.f;
+    if constexpr (Fz<K, G>::LQ && ST == Fz<K, G>::S - 1) {
+        // qubit K-1 across lanes; its term is taken on the values before the undo, with
+        // the weight before this qubit
+        float a = 0.f;
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 fq = lane_x1(f[r]);
+            const float2 lq = lane_x1(l[r]);
+            cacc(a, 1.f, l[r], fq);
+            f[r] = make_float2(fmaf(-t, fq.y, f[r].x), fmaf(t, fq.x, f[r].y));
+            l[r] = make_float2(fmaf(-t, lq.y, l[r].x), fmaf(t, lq.x, l[r].y));
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        acc = w * a;
+        w *= k2;
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
         if (ST * AB + i >= K) continue;
