@@ -162,9 +162,20 @@ __device__ __forceinline__ void hxpose_dual(float2 (&f)[A], float2 (&l)[A], floa
 
 // Mixer on the processed tile bits of layout ROT (tile bit b is processed when bit b of
 // pm is set; a butterfly with tau = 0 is the identity).  Wrapped bits belong to rotation 0.
-template <int CF, int ROT, int A>
+template <int CF, int ROT, int LB = -1, int A>
 __device__ __forceinline__ void hmix(float2 (&v)[A], float t, uint32_t pm) {
     constexpr int AB = Hz<CF>::AB;
+    if constexpr (LB >= 0) {
+        // tile bit LB sits on lane bit 0 of this layout: partner in the neighbouring lane
+        const float ti = ((pm >> LB) & 1u) ? t : 0.f;
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 q = lane_x1(v[r]);
+            v[r] = make_float2(fmaf(ti, q.y, v[r].x), fmaf(-ti, q.x, v[r].y));
+            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
         if (ROT + i >= HT) continue;
@@ -182,10 +193,28 @@ __device__ __forceinline__ void hmix(float2 (&v)[A], float t, uint32_t pm) {
 
 // Undo the mixer on the processed bits of layout ROT for psi and lambda; returns the
 // weighted share of Im <lambda| sum_j X_j |psi> (see unmix_stage2).
-template <int CF, int ROT, int A>
+template <int CF, int ROT, int LB = -1, int A>
 __device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w, uint32_t pm) {
     constexpr int AB = Hz<CF>::AB;
     float acc = 0.f;
+    if constexpr (LB >= 0) {
+        // lane bit 0: term on the values before the undo, with the weight before this bit
+        const bool act = (pm >> LB) & 1u;
+        const float ti = act ? -t : 0.f;
+        float a = 0.f;
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 fq = lane_x1(f[r]);
+            const float2 lq = lane_x1(l[r]);
+            cacc(a, 1.f, l[r], fq);
+            f[r] = make_float2(fmaf(ti, fq.y, f[r].x), fmaf(-ti, fq.x, f[r].y));
+            l[r] = make_float2(fmaf(ti, lq.y, l[r].x), fmaf(-ti, lq.x, l[r].y));
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        acc = act ? w * a : 0.f;
+        w = act ? w * k2 : w;
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
         if (ROT + i >= HT) continue;
@@ -212,12 +241,15 @@ __device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t
 }
 
 // Processing layouts: rotations 0, AB, 2 AB, ...  Group 0 needs all 13 tile bits,
-// groups >= 1 at most 9 (tile bits 0..8).
+// groups >= 1 at most 9 (tile bits 0..8).  With NB = S AB + 1 the leftover bit NB-1 is
+// lane bit 0 of the last layout and is mixed across lanes there (LB).
 template <int CF, bool G0>
 struct HStages {
     static constexpr int AB = Hz<CF>::AB;
     static constexpr int NB = G0 ? HT : 9;
-    static constexpr int S = (NB + AB - 1) / AB;
+    static constexpr bool LQ = NB % AB == 1 && NB / AB >= 2;
+    static constexpr int S = LQ ? NB / AB : (NB + AB - 1) / AB;
+    static constexpr int LB = LQ ? NB - 1 : -1;
     static constexpr int rot(int s) { return s * AB; }
     static constexpr int IO = G0 ? Hz<CF>::ROT_IO0 : Hz<CF>::ROT_IOJ;
 };
@@ -232,7 +264,7 @@ __device__ __forceinline__ void hmix_group(float2 (&f)[A], float2* xb, uint32_t 
         constexpr int st = DESC ? H::S - 1 - j : j;
         constexpr int prev = (j == 0) ? FROM_ROT : H::rot(DESC ? H::S - j : j - 1);
         if constexpr (prev != H::rot(st)) hxpose<CF, prev, H::rot(st)>(f, xb, tau);
-        hmix<CF, H::rot(st)>(f, t, pm);
+        hmix<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1)>(f, t, pm);
     });
 }
 
@@ -253,7 +285,7 @@ __device__ __forceinline__ float hunmix_group(float2 (&f)[A], float2 (&l)[A], fl
                 hxpose<CF, prev, H::rot(st)>(l, xb, tau);
             }
         }
-        acc += hunmix2<CF, H::rot(st)>(f, l, t, k2, w, pm);
+        acc += hunmix2<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1)>(f, l, t, k2, w, pm);
     });
     return acc;
 }
