@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace qaoa {
 namespace {
@@ -212,63 +213,102 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
         }
     }
 
-    // ---- light cones
+    // ---- light cones.  Every cone depends only on the graph, so the orbits are split into
+    // contiguous ranges over threads; a failure reports the lowest failing orbit, as a
+    // serial walk would.
     const int32_t kmax = opt.max_cone_qubits;
-    std::vector<int32_t> mark(n, -1), dist(n, 0), loc(n, -1);
-    P.cones.resize(P.rep.size());
-    P.cut_min = 0;
-    P.cut_max = 0;
-    for (size_t o = 0; o < P.rep.size(); ++o) {
-        const int64_t e0 = P.rep[o];
-        const int32_t a0 = P.u[e0], b0 = P.v[e0];
-        const int32_t stamp = static_cast<int32_t>(o);
-        std::vector<int32_t> ball{a0, b0};
-        mark[a0] = mark[b0] = stamp;
-        dist[a0] = dist[b0] = 0;
-        size_t lo = 0;
-        for (int32_t d = 1; d <= p; ++d) {
-            const size_t hi = ball.size();
-            for (size_t t = lo; t < hi; ++t) {
-                const int32_t x = ball[t];
+    const int64_t M = static_cast<int64_t>(P.rep.size());
+    P.cones.resize(static_cast<size_t>(M));
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t nt = M >= 4096 ? std::min<int64_t>({8, hw, M / 1024}) : 1;
+    std::vector<int64_t> fail_at(static_cast<size_t>(nt), -1);
+    std::vector<PlanError> fail_err(static_cast<size_t>(nt));
+    auto extract = [&](int64_t t) {
+        std::vector<int32_t> mark(n, -1), dist(n, 0), loc(n, -1), ball;
+        ball.reserve(static_cast<size_t>(kmax) + 1);
+        const int64_t o_end = (t + 1) * M / nt;
+        for (int64_t o = t * M / nt; o < o_end; ++o) {
+            const int64_t e0 = P.rep[o];
+            const int32_t a0 = P.u[e0], b0 = P.v[e0];
+            const int32_t stamp = static_cast<int32_t>(o);
+            ball.assign({a0, b0});
+            mark[a0] = mark[b0] = stamp;
+            dist[a0] = dist[b0] = 0;
+            size_t lo = 0;
+            for (int32_t d = 1; d <= p; ++d) {
+                const size_t hi = ball.size();
+                for (size_t q = lo; q < hi; ++q) {
+                    const int32_t x = ball[q];
+                    for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+                        const int32_t y = nbr[j];
+                        if (mark[y] != stamp) {
+                            mark[y] = stamp;
+                            dist[y] = d;
+                            ball.push_back(y);
+                            if (static_cast<int32_t>(ball.size()) > kmax) {
+                                fail_at[t] = o;
+                                fail_err[t] = PlanError{kECONE, "light cone of orbit " + std::to_string(o) + " (edge " +
+                                                                     std::to_string(e0) + ") exceeds " +
+                                                                     std::to_string(kmax) + " qubits"};
+                                return;
+                            }
+                        }
+                    }
+                }
+                lo = hi;
+            }
+            std::sort(ball.begin() + 2, ball.end(), [&](int32_t x, int32_t y) {
+                return dist[x] != dist[y] ? dist[x] < dist[y] : x < y;
+            });
+            Cone& c = P.cones[o];
+            c.k = static_cast<int32_t>(ball.size());
+            c.nodes.assign(ball.begin(), ball.end());
+            for (int32_t i = 0; i < c.k; ++i) loc[ball[i]] = i;
+            int64_t cmin = 0, cmax = 0, ne = 0;
+            for (int32_t i = 0; i < c.k; ++i) {
+                const int32_t x = ball[i];
+                for (int64_t j = off[x]; j < off[x + 1]; ++j)
+                    if (mark[nbr[j]] == stamp && loc[nbr[j]] > i) ++ne;
+            }
+            c.ea.reserve(ne);
+            c.eb.reserve(ne);
+            c.ew.reserve(ne);
+            for (int32_t i = 0; i < c.k; ++i) {
+                const int32_t x = ball[i];
                 for (int64_t j = off[x]; j < off[x + 1]; ++j) {
                     const int32_t y = nbr[j];
-                    if (mark[y] != stamp) {
-                        mark[y] = stamp;
-                        dist[y] = d;
-                        ball.push_back(y);
-                        if (static_cast<int32_t>(ball.size()) > kmax)
-                            fail(kECONE, "light cone of orbit " + std::to_string(o) + " (edge " + std::to_string(e0) +
-                                         ") exceeds " + std::to_string(kmax) + " qubits");
+                    if (mark[y] == stamp && loc[y] > i) {
+                        c.ea.push_back(i);
+                        c.eb.push_back(loc[y]);
+                        const int32_t wi = P.wi[nbr_e[j]];
+                        c.ew.push_back(wi);
+                        if (wi < 0) cmin += wi; else cmax += wi;
                     }
                 }
             }
-            lo = hi;
-        }
-        std::sort(ball.begin() + 2, ball.end(), [&](int32_t x, int32_t y) {
-            return dist[x] != dist[y] ? dist[x] < dist[y] : x < y;
-        });
-        Cone& c = P.cones[o];
-        c.k = static_cast<int32_t>(ball.size());
-        c.nodes = ball;
-        for (int32_t i = 0; i < c.k; ++i) loc[ball[i]] = i;
-        int64_t cmin = 0, cmax = 0;
-        for (int32_t i = 0; i < c.k; ++i) {
-            const int32_t x = ball[i];
-            for (int64_t j = off[x]; j < off[x + 1]; ++j) {
-                const int32_t y = nbr[j];
-                if (mark[y] == stamp && loc[y] > i) {
-                    c.ea.push_back(i);
-                    c.eb.push_back(loc[y]);
-                    const int32_t wi = P.wi[nbr_e[j]];
-                    c.ew.push_back(wi);
-                    if (wi < 0) cmin += wi; else cmax += wi;
-                }
+            if (cmax - cmin > 255) {
+                fail_at[t] = o;
+                fail_err[t] = PlanError{kECONE, "cut values of the cone of orbit " + std::to_string(o) +
+                                                    " span more than 255 integers"};
+                return;
             }
+            c.cut_min = static_cast<int32_t>(cmin);
+            c.cut_max = static_cast<int32_t>(cmax);
         }
-        if (cmax - cmin > 255)
-            fail(kECONE, "cut values of the cone of orbit " + std::to_string(o) + " span more than 255 integers");
-        c.cut_min = static_cast<int32_t>(cmin);
-        c.cut_max = static_cast<int32_t>(cmax);
+    };
+    if (nt == 1) {
+        extract(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int64_t t = 1; t < nt; ++t) pool.emplace_back(extract, t);
+        extract(0);
+        for (auto& th : pool) th.join();
+    }
+    for (int64_t t = 0; t < nt; ++t)
+        if (fail_at[t] >= 0) throw fail_err[t];   // ranges are ascending: the first is the lowest
+    P.cut_min = 0;
+    P.cut_max = 0;
+    for (const Cone& c : P.cones) {
         P.cut_min = std::min<int32_t>(P.cut_min, c.cut_min);
         P.cut_max = std::max<int32_t>(P.cut_max, c.cut_max);
     }

@@ -43,6 +43,8 @@ PLANNER_CASES = [
     ("paley13", lambda: W.paley(13), 1),
     ("torus3d-4", lambda: W.torus3d(4), 1),
     ("rook5", lambda: W.rook(5), 1),
+    # 4500 orbits: enough for the planner to split the cones over threads
+    ("rand3-3000", lambda: W.random_regular(3000, 3, 7), 2),
 ]
 
 
@@ -148,3 +150,27 @@ def test_empty_and_isolated():
     assert pl.info()["n_orbits"] == 0
     pl = Q.Plan(6, [[0, 1], [3, 4]], p=3)
     assert pl.info()["k_hist"][2] == 2
+
+
+def test_first_failing_cone_is_reported():
+    # cones are extracted on several threads for large plans; the error must still name
+    # the lowest failing orbit.  Random 3-regular, p = 2: every cone has more than 6 qubits
+    # except those closed off by short cycles, so orbit 0 is the first to fail.
+    g = W.random_regular(6000, 3, 11)
+    ref = oracle.plan(g.n, g.edges, None, None, 2, reduce=True, max_k=40)
+    first = next(m for m, c in enumerate(ref["cones"]) if c["k"] > 6)
+    with pytest.raises(Q.QaoaError) as ei:
+        Q.Plan(g.n, g.edges, p=2, max_cone_qubits=6)
+    assert ei.value.status == Q.QAOA_ECONE
+    assert f"light cone of orbit {first} " in str(ei.value)
+    # a cut-range failure far into the orbit list: weight 300 on one late edge; the first
+    # cone holding both of its ends fails
+    w = np.ones(g.m)
+    x, y = (int(t) for t in g.edges[g.m - 5])
+    w[g.m - 5] = 300.0
+    with pytest.raises(Q.QaoaError) as ei:
+        Q.Plan(g.n, g.edges, p=1, weights=w)
+    assert ei.value.status == Q.QAOA_ECONE
+    cones = oracle.plan(g.n, g.edges, None, None, 1, reduce=True, max_k=40)["cones"]
+    bad = [m for m, c in enumerate(cones) if x in c["nodes"] and y in c["nodes"]]
+    assert f"cone of orbit {min(bad)} " in str(ei.value)
