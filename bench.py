@@ -412,6 +412,8 @@ def main():
     line.update(extra)
     if a.hbm_points > 0:
         line["hbm"] = hbm_measure(Q, torch, W, a.hbm_points)
+        # context for the HBM fraction: what a plain 4 GiB device-to-device copy reaches here
+        line["hbm"]["device_copy_GBps"] = copy_measure(torch, 4.0)["GBps_read_plus_write"]
     if a.copy_gib > 0:
         line["copy"] = copy_measure(torch, a.copy_gib)
     if not a.no_cpu_baseline:
