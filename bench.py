@@ -29,13 +29,13 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "e7e0869c6f34276dc342346b225693e043995ff88628920adbaac05ec45ecb87",
-               "counted_over_algorithmic": 1.018}
+HBM_TRAFFIC = {"sources_sha256": "5639ee30d2bf4157528c19ff7fbc0b4ca5ef622a40aaade0610a60bfcf55975f",
+               "counted_over_algorithmic": 1.005}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
 # item (cut tables and phase rows read, five FP64 results written).
-FUSED_TRAFFIC = {"sources_sha256": "eaa44ab50f60a92dad8eb84266d46a602a1567555d530909f8cfcd76c74d2409",
+FUSED_TRAFFIC = {"sources_sha256": "e7c1ebef6b8c46eedb67c462266cc5d9f29a0ae24f1ab23fe744c13e77d36919",
                  "bytes_per_item": 297.5}
 
 
@@ -49,7 +49,8 @@ def sources_sha256(files) -> str:
 
 
 def hbm_sources_sha256() -> str:
-    return sources_sha256(("paper_2101_10296_amd/csrc/hbm_impl.hpp", "paper_2101_10296_amd/csrc/hbm.hip"))
+    return sources_sha256(("paper_2101_10296_amd/csrc/hbm_impl.hpp", "paper_2101_10296_amd/csrc/hbm.hip",
+                           "paper_2101_10296_amd/csrc/fused_impl.hpp"))
 
 
 def fused_sources_sha256() -> str:

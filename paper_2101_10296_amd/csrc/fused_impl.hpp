@@ -53,7 +53,7 @@ struct Fz {
     static constexpr bool LQ = K % AB == 1 && K / AB >= 2;
     static constexpr int S = LQ ? K / AB : (K + AB - 1) / AB;   // stages
     static constexpr uint32_t N = 1u << K;
-    static constexpr uint32_t NPAD = N + (N >> 5) + (N >> 10);  // padded LDS item buffer
+    static constexpr uint32_t NPAD = N + (N >> 4) + (N >> 8) + 8 * (N >> 12);  // padded LDS item buffer
 };
 
 template <int K>
@@ -65,10 +65,13 @@ __device__ constexpr uint32_t roff(int r) { return rotl<K>(static_cast<uint32_t>
 template <int K, int G, int ST>
 __device__ __forceinline__ uint32_t tbase(uint32_t tau) { return rotl<K>(tau << Fz<K, G>::AB, ST * Fz<K, G>::AB); }
 
-// LDS padding against bank conflicts: one slot per 32 and one per 1024 entries.  It is
-// additive over indices with disjoint bits, so pad(base | off) = pad(base) + pad(off) and
-// every register of a transpose is addressed by one base register plus an immediate.
-__device__ constexpr uint32_t pad(uint32_t q) { return q + (q >> 5) + (q >> 10); }
+// LDS padding against bank conflicts: one slot per 16 and per 256 entries, eight per 4096.
+// With 8-byte entries, the 16 lanes that share an LDS cycle then hit 16 distinct bank pairs
+// in every register stage of the 13-bit adjoint layout (lane bits on qubits 4-7, 8-11 and
+// 12, 0, 1, 2), including the complement partners of the flip transposes.  It is additive
+// over indices with disjoint bits, so pad(base | off) = pad(base) + pad(off) and every
+// register of a transpose is addressed by one base register plus an immediate.
+__device__ constexpr uint32_t pad(uint32_t q) { return q + (q >> 4) + (q >> 8) + 8 * (q >> 12); }
 
 template <int NS, class F>
 __device__ __forceinline__ void sdispatch(int st, F&& f) {

@@ -111,7 +111,7 @@ struct Hz {
     static constexpr int A = 1 << AB;
     static constexpr int W = 1 << (HT - AB);        // threads per tile
     static constexpr int WPE = CF == 0 ? 2 : (CF == 3 ? QAOA_HBM_CF3_WPE : 4);   // minimum waves per SIMD
-    static constexpr uint32_t NPAD = HN + (HN >> 5) + (HN >> 10);
+    static constexpr uint32_t NPAD = HN + (HN >> 4) + (HN >> 8) + 8 * (HN >> 12);   // padded tile buffer (pad())
     static constexpr int ROT_IO0 = HT - AB;          // I/O layout of group 0: lanes on tile bits 0..5
     static constexpr int ROT_IOJ = 9 - AB;           // I/O layout of groups >= 1: lanes on tile bits 9..12, 0, 1
 };
