@@ -53,7 +53,7 @@ struct Fz {
     static constexpr bool LQ = K % AB == 1 && K / AB >= 2;
     static constexpr int S = LQ ? K / AB : (K + AB - 1) / AB;   // stages
     static constexpr uint32_t N = 1u << K;
-    static constexpr uint32_t NPAD = N + (N >> 4) + (N >> 8) + 8 * (N >> 12);  // padded LDS item buffer
+    static constexpr uint32_t NPAD = N + (N >> 4) + (N >> 8) + (AB == 5 ? 2 : 8) * (N >> 12);  // padded item buffer
 };
 
 template <int K>
@@ -65,13 +65,15 @@ __device__ constexpr uint32_t roff(int r) { return rotl<K>(static_cast<uint32_t>
 template <int K, int G, int ST>
 __device__ __forceinline__ uint32_t tbase(uint32_t tau) { return rotl<K>(tau << Fz<K, G>::AB, ST * Fz<K, G>::AB); }
 
-// LDS padding against bank conflicts: one slot per 16 and per 256 entries, eight per 4096.
-// With 8-byte entries, the 16 lanes that share an LDS cycle then hit 16 distinct bank pairs
-// in every register stage of the 13-bit adjoint layout (lane bits on qubits 4-7, 8-11 and
-// 12, 0, 1, 2), including the complement partners of the flip transposes.  It is additive
-// over indices with disjoint bits, so pad(base | off) = pad(base) + pad(off) and every
-// register of a transpose is addressed by one base register plus an immediate.
-__device__ constexpr uint32_t pad(uint32_t q) { return q + (q >> 4) + (q >> 8) + 8 * (q >> 12); }
+// LDS padding against bank conflicts: one slot per 16 and per 256 entries, and c per 4096
+// (c = 8 for 4 register bits per stage, 2 for 5).  With 8-byte entries the 16 lanes that
+// share an LDS cycle then hit 16 distinct bank pairs in every register stage of the 13-bit
+// layouts (lane bits on qubits 4-7, 8-11, 12 0 1 2 for AB = 4; 5-8, 10 11 12 0, 2-5 for
+// AB = 5), including the complement partners of the flip transposes.  It is additive over
+// indices with disjoint bits, so pad(base | off) = pad(base) + pad(off) and every register
+// of a transpose is addressed by one base register plus an immediate.
+template <int AB = 4>
+__device__ constexpr uint32_t pad(uint32_t q) { return q + (q >> 4) + (q >> 8) + (AB == 5 ? 2u : 8u) * (q >> 12); }
 
 template <int NS, class F>
 __device__ __forceinline__ void sdispatch(int st, F&& f) {
@@ -214,14 +216,14 @@ __device__ __forceinline__ uint32_t opaque_u32(uint32_t x) {
 
 template <int K, int G, int FROM, int TO, int A>
 __device__ __forceinline__ void xpose(float2 (&v)[A], float2* xb, uint32_t tau) {
-    float2* pf = xb + opaque_u32(pad(tbase<K, G, FROM>(tau)));
-    const float2* pt = xb + opaque_u32(pad(tbase<K, G, TO>(tau)));
+    float2* pf = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, FROM>(tau)));
+    const float2* pt = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(tau)));
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = v[r];
+    for (int r = 0; r < A; ++r) pf[pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = v[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) v[r] = pt[pad(roff<K, G, TO>(r))];
+    for (int r = 0; r < A; ++r) v[r] = pt[pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
 }
 
 
@@ -233,17 +235,17 @@ __device__ __forceinline__ void xpose(float2 (&v)[A], float2* xb, uint32_t tau) 
 template <int K, int G, int FROM, int TO, int A>
 __device__ __forceinline__ void xpose_flip(float2 (&v)[A], float2* xb, uint32_t tau, float t) {
     constexpr uint32_t TM = Fz<K, G>::TPI - 1;
-    float2* pf = xb + opaque_u32(pad(tbase<K, G, FROM>(tau)));
-    const float2* pt = xb + opaque_u32(pad(tbase<K, G, TO>(tau)));
-    const float2* pc = xb + opaque_u32(pad(tbase<K, G, TO>(~tau & TM)));
+    float2* pf = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, FROM>(tau)));
+    const float2* pt = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(tau)));
+    const float2* pc = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(~tau & TM)));
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = v[r];
+    for (int r = 0; r < A; ++r) pf[pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = v[r];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        const float2 a = pt[pad(roff<K, G, TO>(r))];
-        const float2 b = pc[pad(roff<K, G, TO>(A - 1 - r))];
+        const float2 a = pt[pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
+        const float2 b = pc[pad<Fz<K, G>::AB>(roff<K, G, TO>(A - 1 - r))];
         v[r] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
@@ -255,29 +257,29 @@ __device__ __forceinline__ void xpose_flip(float2 (&v)[A], float2* xb, uint32_t 
 template <int K, int G, int FROM, int TO, int A>
 __device__ __forceinline__ float xpose2_unflip(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, float t) {
     constexpr uint32_t TM = Fz<K, G>::TPI - 1;
-    float2* pf = xb + opaque_u32(pad(tbase<K, G, FROM>(tau)));
-    const float2* pt = xb + opaque_u32(pad(tbase<K, G, TO>(tau)));
-    const float2* pc = xb + opaque_u32(pad(tbase<K, G, TO>(~tau & TM)));
+    float2* pf = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, FROM>(tau)));
+    const float2* pt = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(tau)));
+    const float2* pc = xb + opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(~tau & TM)));
     float2 fp[A];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = f[r];
+    for (int r = 0; r < A; ++r) pf[pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = f[r];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        f[r] = pt[pad(roff<K, G, TO>(r))];
-        fp[r] = pc[pad(roff<K, G, TO>(A - 1 - r))];
+        f[r] = pt[pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
+        fp[r] = pc[pad<Fz<K, G>::AB>(roff<K, G, TO>(A - 1 - r))];
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) pf[pad(roff<K, G, FROM>(r))] = l[r];
+    for (int r = 0; r < A; ++r) pf[pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = l[r];
     __syncthreads();
     float acc = 0.f;
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        const float2 lo = pt[pad(roff<K, G, TO>(r))];
-        const float2 lq = pc[pad(roff<K, G, TO>(A - 1 - r))];
+        const float2 lo = pt[pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
+        const float2 lq = pc[pad<Fz<K, G>::AB>(roff<K, G, TO>(A - 1 - r))];
         cacc(acc, 1.f, lo, fp[r]);
         l[r] = make_float2(fmaf(-t, lq.y, lo.x), fmaf(t, lq.x, lo.y));
         f[r] = make_float2(fmaf(-t, fp[r].y, f[r].x), fmaf(t, fp[r].x, f[r].y));
@@ -291,19 +293,19 @@ __device__ __forceinline__ float xpose2_unflip(float2 (&f)[A], float2 (&l)[A], f
 // one barrier pair instead of two.
 template <int K, int G, int FROM, int TO, int A>
 __device__ __forceinline__ void xpose_dual(float2 (&f)[A], float2 (&l)[A], float2* xa, float2* xc, uint32_t tau) {
-    const uint32_t of = opaque_u32(pad(tbase<K, G, FROM>(tau)));
-    const uint32_t ot = opaque_u32(pad(tbase<K, G, TO>(tau)));
+    const uint32_t of = opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, FROM>(tau)));
+    const uint32_t ot = opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(tau)));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        xa[of + pad(roff<K, G, FROM>(r))] = f[r];
-        xc[of + pad(roff<K, G, FROM>(r))] = l[r];
+        xa[of + pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = f[r];
+        xc[of + pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = l[r];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        f[r] = xa[ot + pad(roff<K, G, TO>(r))];
-        l[r] = xc[ot + pad(roff<K, G, TO>(r))];
+        f[r] = xa[ot + pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
+        l[r] = xc[ot + pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
     }
 }
 
@@ -311,23 +313,23 @@ template <int K, int G, int FROM, int TO, int A>
 __device__ __forceinline__ float xpose2_unflip_dual(float2 (&f)[A], float2 (&l)[A], float2* xa, float2* xc,
                                                     uint32_t tau, float t) {
     constexpr uint32_t TM = Fz<K, G>::TPI - 1;
-    const uint32_t of = opaque_u32(pad(tbase<K, G, FROM>(tau)));
-    const uint32_t ot = opaque_u32(pad(tbase<K, G, TO>(tau)));
-    const uint32_t oc = opaque_u32(pad(tbase<K, G, TO>(~tau & TM)));
+    const uint32_t of = opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, FROM>(tau)));
+    const uint32_t ot = opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(tau)));
+    const uint32_t oc = opaque_u32(pad<Fz<K, G>::AB>(tbase<K, G, TO>(~tau & TM)));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        xa[of + pad(roff<K, G, FROM>(r))] = f[r];
-        xc[of + pad(roff<K, G, FROM>(r))] = l[r];
+        xa[of + pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = f[r];
+        xc[of + pad<Fz<K, G>::AB>(roff<K, G, FROM>(r))] = l[r];
     }
     __syncthreads();
     float acc = 0.f;
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        const float2 fo = xa[ot + pad(roff<K, G, TO>(r))];
-        const float2 fq = xa[oc + pad(roff<K, G, TO>(A - 1 - r))];
-        const float2 lo = xc[ot + pad(roff<K, G, TO>(r))];
-        const float2 lq = xc[oc + pad(roff<K, G, TO>(A - 1 - r))];
+        const float2 fo = xa[ot + pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
+        const float2 fq = xa[oc + pad<Fz<K, G>::AB>(roff<K, G, TO>(A - 1 - r))];
+        const float2 lo = xc[ot + pad<Fz<K, G>::AB>(roff<K, G, TO>(r))];
+        const float2 lq = xc[oc + pad<Fz<K, G>::AB>(roff<K, G, TO>(A - 1 - r))];
         cacc(acc, 1.f, lo, fq);
         l[r] = make_float2(fmaf(-t, lq.y, lo.x), fmaf(t, lq.x, lo.y));
         f[r] = make_float2(fmaf(-t, fq.y, fo.x), fmaf(t, fq.x, fo.y));
