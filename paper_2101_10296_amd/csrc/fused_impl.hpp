@@ -31,6 +31,7 @@
 
 #include "device.hpp"
 
+#include <atomic>
 #include <type_traits>
 
 namespace qaoa {
@@ -699,17 +700,20 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
 }
 
 // ---------------------------------------------------------------- launcher
-// LDS bytes a kernel variant declares statically (queried once per variant)
+// LDS bytes a kernel variant declares statically (queried once per variant; concurrent
+// first calls may both query, which is harmless)
 template <int K, bool GRAD, bool ODD, bool DB, bool GR>
 hipError_t static_lds(size_t& out) {
-    static size_t bytes = 0;   // + 1 once queried
-    if (!bytes) {
+    static std::atomic<size_t> bytes{0};   // + 1 once queried
+    size_t b = bytes.load(std::memory_order_relaxed);
+    if (!b) {
         hipFuncAttributes fa{};
         const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, GRAD, ODD, DB, GR>));
         if (e != hipSuccess) return e;
-        bytes = fa.sharedSizeBytes + 1;
+        b = fa.sharedSizeBytes + 1;
+        bytes.store(b, std::memory_order_relaxed);
     }
-    out = bytes - 1;
+    out = b - 1;
     return hipSuccess;
 }
 

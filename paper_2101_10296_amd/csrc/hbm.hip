@@ -78,14 +78,16 @@ static hipError_t launch_one(const PassArgs& pa, hipStream_t st) {
     const size_t dyn = 3 * static_cast<size_t>(pa.rowcap) * sizeof(float2);   // three phase rows
     if constexpr (CF == 3) {
         // two LDS buffers when they fit beside the phase rows
-        static size_t db_static = 0;
-        if (!db_static) {
+        static std::atomic<size_t> db_static{0};   // + 1 once queried
+        size_t db = db_static.load(std::memory_order_relaxed);
+        if (!db) {
             hipFuncAttributes fa{};
             const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_pass<KIND, G0, true>));
             if (e != hipSuccess) return e;
-            db_static = fa.sharedSizeBytes;
+            db = fa.sharedSizeBytes + 1;
+            db_static.store(db, std::memory_order_relaxed);
         }
-        if (db_static + dyn <= 160 * 1024) {
+        if (db - 1 + dyn <= 160 * 1024) {
             hipLaunchKernelGGL((k_pass<KIND, G0, true>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<CF>::W), dyn, st,
                                pa);
             return hipGetLastError();

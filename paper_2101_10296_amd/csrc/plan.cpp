@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <numeric>
 #include <thread>
 
@@ -223,7 +224,8 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
     const int64_t nt = M >= 4096 ? std::min<int64_t>({8, hw, M / 1024}) : 1;
     std::vector<int64_t> fail_at(static_cast<size_t>(nt), -1);
     std::vector<PlanError> fail_err(static_cast<size_t>(nt));
-    auto extract = [&](int64_t t) {
+    std::vector<char> no_mem(static_cast<size_t>(nt), 0);
+    auto extract_range = [&](int64_t t) {
         std::vector<int32_t> mark(n, -1), dist(n, 0), loc(n, -1), ball;
         ball.reserve(static_cast<size_t>(kmax) + 1);
         const int64_t o_end = (t + 1) * M / nt;
@@ -296,6 +298,14 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
             c.cut_max = static_cast<int32_t>(cmax);
         }
     };
+    // an allocation failure on a worker thread is carried to the caller's thread
+    auto extract = [&](int64_t t) {
+        try {
+            extract_range(t);
+        } catch (const std::bad_alloc&) {
+            no_mem[t] = 1;
+        }
+    };
     if (nt == 1) {
         extract(0);
     } else {
@@ -304,6 +314,8 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
         extract(0);
         for (auto& th : pool) th.join();
     }
+    for (int64_t t = 0; t < nt; ++t)
+        if (no_mem[t]) throw std::bad_alloc();
     for (int64_t t = 0; t < nt; ++t)
         if (fail_at[t] >= 0) throw fail_err[t];   // ranges are ascending: the first is the lowest
     P.cut_min = 0;
