@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <system_error>
 #include <thread>
 
 namespace qaoa {
@@ -310,7 +311,16 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
         extract(0);
     } else {
         std::vector<std::thread> pool;
-        for (int64_t t = 1; t < nt; ++t) pool.emplace_back(extract, t);
+        int64_t started = 1;
+        try {
+            for (int64_t t = 1; t < nt; ++t) {
+                pool.emplace_back(extract, t);
+                started = t + 1;
+            }
+        } catch (const std::system_error&) {
+            // no more threads: the remaining ranges run here
+        }
+        for (int64_t t = started; t < nt; ++t) extract(t);
         extract(0);
         for (auto& th : pool) th.join();
     }
