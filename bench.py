@@ -6,7 +6,7 @@ Workload (default): the p=2 pair of graphs with a batch of 256 angle points each
 One step = plan both graphs (orbits + light cones + device tables) and evaluate the energy
 and its gradient at all 256 points of each.  value = (graph, point) evaluations per second.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the library drives one GPU (no sharding).
 """
 from __future__ import annotations
 
@@ -291,7 +291,7 @@ def main():
                     help="also time a device-to-device copy of this many GiB (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library drives one GPU (no sharding across GPUs); --gpus must be 1"}))
         sys.exit(2)
 
     import torch
