@@ -61,10 +61,10 @@ __global__ void k_cut_tables(const ConeDev* __restrict__ cones, const int32_t* _
 // Fixed-order reduction (deterministic): thread t sums m = t, t + 256, ...; then a tree.
 __global__ void __launch_bounds__(256)
 k_combine(const double* __restrict__ W, const double* __restrict__ zz, const double* __restrict__ g,
-          int32_t M, int32_t p, double delta, double* __restrict__ energy, double* __restrict__ dgamma,
+          int32_t M, int32_t p, double delta, int64_t i0, double* __restrict__ energy, double* __restrict__ dgamma,
           double* __restrict__ dbeta) {
     __shared__ double sh[256];
-    const int i = blockIdx.x;
+    const int64_t i = i0 + blockIdx.x;
     const int y = blockIdx.y;
     const double* src = (y == 0) ? zz + static_cast<size_t>(i) * M
                                  : g + (static_cast<size_t>(i) * 2 * p + (y - 1)) * M;
@@ -97,18 +97,30 @@ hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, 
 
 hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
                              const int32_t* ew, uint8_t* tables, hipStream_t st) {
-    if (n_cones <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cut_tables, dim3(static_cast<unsigned>(n_cones)), dim3(256), 0, st, cones, ea, eb, ew,
-                       tables);
-    return hipGetLastError();
+    // one block per cone; a grid holds fewer than 2^32 threads
+    constexpr int64_t CH = static_cast<int64_t>(UINT32_MAX) / 256;
+    for (int64_t c0 = 0; c0 < n_cones; c0 += CH) {
+        const unsigned nx = static_cast<unsigned>(n_cones - c0 < CH ? n_cones - c0 : CH);
+        hipLaunchKernelGGL(k_cut_tables, dim3(nx), dim3(256), 0, st, cones + c0, ea, eb, ew, tables);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
                           double delta, double* energy, double* dgamma, double* dbeta, hipStream_t st) {
     const unsigned ny = (g != nullptr) ? static_cast<unsigned>(1 + 2 * p) : 1u;
-    hipLaunchKernelGGL(k_combine, dim3(static_cast<unsigned>(P), ny), dim3(256), 0, st, W, zz, g, M, p, delta,
-                       energy, dgamma, dbeta);
-    return hipGetLastError();
+    // one block per point; a grid holds fewer than 2^32 threads
+    constexpr int64_t CH = static_cast<int64_t>(UINT32_MAX) / 256;
+    for (int64_t i0 = 0; i0 < P; i0 += CH) {
+        const unsigned nx = static_cast<unsigned>(P - i0 < CH ? P - i0 : CH);
+        hipLaunchKernelGGL(k_combine, dim3(nx, ny), dim3(256), 0, st, W, zz, g, M, p, delta, i0, energy, dgamma,
+                           dbeta);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace qaoa

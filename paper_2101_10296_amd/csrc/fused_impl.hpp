@@ -31,6 +31,7 @@
 
 #include "device.hpp"
 
+#include <algorithm>
 #include <atomic>
 #include <type_traits>
 
@@ -753,13 +754,23 @@ hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t 
     const int64_t blocks = (todo + ipw - 1) / ipw;
     if (blocks <= 0) return hipSuccess;
     const size_t dyn = static_cast<size_t>(ipw) * ea.p * rowcap * sizeof(float2);
-    const dim3 grid(static_cast<unsigned>(blocks)), block(wg);
+    const dim3 block(wg);
     const bool odd = ((ea.p - 1) & 1) != 0;
-    if (grad)
-        return odd ? launch_v<K, true, true>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st)
-                   : launch_v<K, true, false>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st);
-    return odd ? launch_v<K, false, true>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st)
-               : launch_v<K, false, false>(grid, block, dyn, cones, item_base, n_items, cut, rowcap, ea, st);
+    // a grid holds fewer than 2^32 threads (work-items): larger batches take several launches
+    const int64_t max_blocks = static_cast<int64_t>(UINT32_MAX) / wg;
+    for (int64_t b0 = 0; b0 < blocks; b0 += max_blocks) {
+        const dim3 grid(static_cast<unsigned>(std::min(max_blocks, blocks - b0)));
+        const int64_t base = item_base + b0 * ipw;
+        hipError_t e;
+        if (grad)
+            e = odd ? launch_v<K, true, true>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
+                    : launch_v<K, true, false>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
+        else
+            e = odd ? launch_v<K, false, true>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
+                    : launch_v<K, false, false>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace qaoa

@@ -355,6 +355,8 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
             return QAOA_ENOMEM;
         }
         B = std::min<int64_t>(B, items);
+        // a pass launches up to tiles * B workgroups of <= 512 threads: keep the grid below 2^31
+        B = std::min<int64_t>(B, std::max<int64_t>(1, (int64_t{1} << 22) / tiles));
         // free memory can be fragmented or held by other allocators: on a failed allocation
         // the batch is halved until one item does not fit either
         for (;;) {

@@ -196,6 +196,37 @@ def test_config2ii_full_batch_sampled_terms(Q):
     assert torch.isfinite(dg).all() and torch.isfinite(db).all()
 
 
+def test_batches_beyond_one_grid(Q):
+    # 15000 cones x 600 points = 9.0 M workgroups of 512 threads at 14 qubits: more
+    # work-items than one grid holds (2^32), so the launch is split.  Points whose items
+    # fall on either side of the split must come out identical to a small call.
+    (g, p), = W.workload("c2ii")[0]
+    ga, be = W.draw_angles(600, p, 91)
+    pl = Q.Plan(g.n, g.edges, p=p)
+    assert pl.info()["k_hist"][14] * 600 * 512 > 2 ** 32
+    E, dg, db = pl.energy_grad(dev(ga), dev(be))
+    idx = [0, 6, 7, 8, 599]   # the split falls inside one cone's run of points (item 2^32 / 512)
+    E2, dg2, db2 = pl.energy_grad(dev(ga[idx]), dev(be[idx]))
+    assert torch.equal(E[idx], E2) and torch.equal(dg[idx], dg2) and torch.equal(db[idx], db2)
+    Ef = pl.energy(dev(ga), dev(be))
+    assert torch.equal(Ef[idx], pl.energy(dev(ga[idx]), dev(be[idx])))
+
+
+def test_points_beyond_one_grid(Q):
+    # 2^24 + 5 points: the per-point combination kernel needs more than one grid
+    g = W.single_edge()
+    P = (1 << 24) + 5
+    ga, be = W.draw_angles(P, 1, 17)
+    pl = Q.Plan(g.n, g.edges, p=1)
+    E, dg, db = pl.energy_grad(dev(ga), dev(be))
+    idx = [0, (1 << 24) - 2, (1 << 24) - 1, 1 << 24, P - 1]
+    E2, dg2, db2 = pl.energy_grad(dev(ga[idx]), dev(be[idx]))
+    assert torch.equal(E[idx], E2) and torch.equal(dg[idx], dg2) and torch.equal(db[idx], db2)
+    ref = oracle.plan(g.n, g.edges, None, None, 1)
+    Eo, _ = oracle.energy(ref, ga[idx], be[idx])
+    assert np.abs(E2.cpu().numpy() - Eo).max() <= ZZ_TOL / 2
+
+
 def test_input_errors(Q):
     g = W.random_regular(12, 3, 1)
     pl = Q.Plan(g.n, g.edges, p=2)
