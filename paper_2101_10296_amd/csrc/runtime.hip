@@ -205,6 +205,11 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         P->hbm_groups.back().count += 1;
         P->hbm_groups.back().rowcap = std::max(P->hbm_groups.back().rowcap, d.cut_range);
     }
+    if (ea.size() > static_cast<size_t>(INT32_MAX) || Mall > INT32_MAX) {
+        msg = "the plan's cones hold " + std::to_string(ea.size()) + " edges over " + std::to_string(Mall) +
+              " orbits; descriptors index both with 32-bit integers";
+        return QAOA_EINVAL;
+    }
     const size_t ne = std::max<size_t>(ea.size(), 1);
     QCHECK(hipMalloc(&P->d_cones, std::max<size_t>(cd.size(), 1) * sizeof(ConeDev)));
     QCHECK(hipMalloc(&P->d_cut, std::max<int64_t>(cut_bytes, 16)));
