@@ -163,8 +163,9 @@ __device__ __forceinline__ void mix_stage(float2 (&v)[A], float t) {
 
 // Undo the mixer on the stage's qubits for psi and lambda; returns the stage's share of
 // Im <lambda| sum_j X_j |psi>.  X_j commutes with its own rotation, so the pair's term is
-// taken after the butterfly; every undone qubit scales both states by 1/|kappa|^2, which
-// the running weight w (= |kappa|^{2m} after m qubits) compensates.
+// taken after the butterfly; every undone qubit scales each state by 1/|kappa| (their inner
+// products by 1/|kappa|^2), which the running weight w (= |kappa|^{2m} after m qubits)
+// compensates.
 template <int K, int G, int ST, int A>
 __device__ __forceinline__ float unmix_stage2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w) {
     constexpr int AB = Fz<K, G>::AB;

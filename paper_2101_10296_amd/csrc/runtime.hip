@@ -362,6 +362,14 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         B = std::min<int64_t>(B, items);
         // a pass launches up to tiles * B workgroups of <= 512 threads: keep the grid below 2^31
         B = std::min<int64_t>(B, std::max<int64_t>(1, (int64_t{1} << 22) / tiles));
+        // tiles (group 0: tile pairs) per workgroup: up to 8 while the class keeps >= 4096
+        // workgroups (16 per CU); fixed per class, so an item's sums run in the same order
+        // whatever the batching
+        int tpw = 1;
+        while (tpw < 8 && 2 * tpw <= tiles / 2 && items * tiles / (2 * tpw) >= 4096) tpw *= 2;
+        // no more items per batch than needed for 2^17 workgroups (512 per CU) per pass:
+        // larger batches hold more memory and gain little
+        if (!fixed_batches) B = std::min<int64_t>(B, std::max<int64_t>(1, ((int64_t{1} << 17) * tpw + tiles - 1) / tiles));
         // free memory can be fragmented or held by other allocators: on a failed allocation
         // the batch is halved until one item does not fit either
         for (;;) {
@@ -380,11 +388,6 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         if (st != QAOA_OK) return st;
         P->hbm_batch[gi] = B;
         const std::vector<PassSpec> prog = hbm_program(k, p, grad);
-        // tiles (group 0: tile pairs) per workgroup: up to 8 while the class keeps >= 4096
-        // workgroups (16 per CU); fixed per class, so an item's sums run in the same order
-        // whatever the batching
-        int tpw = 1;
-        while (tpw < 8 && 2 * tpw <= tiles / 2 && items * tiles / (2 * tpw) >= 4096) tpw *= 2;
         QCHECK(tm.begin(k, items));
         for (int64_t i0 = 0; i0 < items; i0 += B) {
             const int64_t nb = std::min<int64_t>(B, items - i0);
