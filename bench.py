@@ -29,13 +29,13 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "4dd508b39cce29438b0989c9cee37392539fa7dc5792ab4c3401663551fdaca2",
+HBM_TRAFFIC = {"sources_sha256": "0097d27763273488efe85dc53f9282811bf3edd72fef5b102dc693246a02696e",
                "counted_over_algorithmic": 1.005}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
 # item (cut tables and phase rows read, five FP64 results written).
-FUSED_TRAFFIC = {"sources_sha256": "da4d519bbc66edb572e4dbcdb13447c245309c814e36519ecd7dbefdacda1201",
+FUSED_TRAFFIC = {"sources_sha256": "086c8c796907f68fc4bd0b14f3a3ce0e5c1691c6f3ed6f044f5bd80c56d96f11",
                  "bytes_per_item": 297.5}
 
 
