@@ -2,10 +2,11 @@
 // construction (the paper takes its symmetry group from an automorphism solver, Sec. 2.6,
 // Sec. 5).  Individualisation and refinement:
 //
-//  * colour refinement: a vertex's new colour is the rank of (its colour, the sorted
-//    multiset of (neighbour colour, edge weight class)) among all vertices, repeated until
-//    no class splits.  Ranks are assigned in sorted signature order, so isomorphic branches
-//    of the search produce the same colours on corresponding vertices;
+//  * colour refinement: a vertex's new colour is the rank of (its colour, a 64-bit hash of
+//    the sorted multiset of (neighbour colour, edge weight class)) among all vertices,
+//    with the multisets themselves compared where two differ under one hash, repeated until
+//    no class splits.  The ranks depend only on the colour data, so isomorphic branches of
+//    the search produce the same colours on corresponding vertices;
 //  * the first (reference) path individualises, at every level, the smallest-id vertex of
 //    the smallest non-singleton class, until the colouring is discrete;
 //  * bottom-up along that path, every other vertex y of the level's target class that is
@@ -29,6 +30,14 @@
 namespace qaoa {
 
 namespace {
+
+// splitmix64 finaliser: the signature hash of a refinement round (an isomorphism-invariant
+// function of the colour data, so ranks by hash are canonical)
+inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
 
 struct AGraph {
     int32_t n = 0;
@@ -58,38 +67,123 @@ class Searcher {
     // classes after some round differs from ref.
     bool refine(Colouring& c, const std::vector<int32_t>* ref) const {
         const int32_t n = g_.n;
-        std::vector<std::vector<uint64_t>> sig(n);
-        std::vector<int32_t> order(n);
+        // colours 0 .. ncol-1 in the order of the input values (canonical)
+        {
+            std::vector<int32_t> vals(c.col);
+            std::sort(vals.begin(), vals.end());
+            vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+            for (int32_t& x : c.col) x = static_cast<int32_t>(std::lower_bound(vals.begin(), vals.end(), x) - vals.begin());
+            c.ncol = static_cast<int32_t>(vals.size());
+        }
+        std::vector<std::vector<int32_t>> cells(c.ncol);
+        std::vector<int32_t> pos(n);
+        for (int32_t v = 0; v < n; ++v) {
+            pos[v] = static_cast<int32_t>(cells[c.col[v]].size());
+            cells[c.col[v]].push_back(v);
+        }
+        std::vector<uint64_t> keys(static_cast<size_t>(g_.off[n]));   // sorted neighbour keys, CSR by g_.off
+        std::vector<uint64_t> h(n);
+        std::vector<int32_t> seen(n, -1), cand(n), changed;
+        std::iota(cand.begin(), cand.end(), 0);
+        auto sign = [&](int32_t v) {
+            const int64_t o = g_.off[v], d = g_.off[v + 1] - o;
+            uint64_t* k = keys.data() + o;
+            for (int64_t j = 0; j < d; ++j)
+                k[j] = (static_cast<uint64_t>(c.col[g_.nbr[o + j]]) << 24) | static_cast<uint64_t>(g_.wcls[o + j]);
+            std::sort(k, k + d);
+            uint64_t x = 0x9e3779b97f4a7c15ull ^ static_cast<uint64_t>(d);
+            for (int64_t j = 0; j < d; ++j) x = mix64(x ^ k[j]);
+            h[v] = x;
+        };
+        // signature order: hash, then the key lists (exact), so a hash collision never merges
+        auto cmp = [&](int32_t a, int32_t b) -> int {
+            if (h[a] != h[b]) return h[a] < h[b] ? -1 : 1;
+            const auto a0 = keys.begin() + g_.off[a], a1 = keys.begin() + g_.off[a + 1];
+            const auto b0 = keys.begin() + g_.off[b], b1 = keys.begin() + g_.off[b + 1];
+            if (std::lexicographical_compare(a0, a1, b0, b1)) return -1;
+            if (std::lexicographical_compare(b0, b1, a0, a1)) return 1;
+            return 0;
+        };
         c.trace.clear();
-        for (int round = 0;; ++round) {
-            for (int32_t v = 0; v < n; ++v) {
-                auto& s = sig[v];
-                s.clear();
-                s.push_back(static_cast<uint64_t>(c.col[v]));
-                for (int64_t j = g_.off[v]; j < g_.off[v + 1]; ++j)
-                    s.push_back((static_cast<uint64_t>(c.col[g_.nbr[j]]) << 24) | static_cast<uint64_t>(g_.wcls[j]));
-                std::sort(s.begin() + 1, s.end());
+        for (int32_t round = 0;; ++round) {
+            // Synchronous rounds: a vertex's signature is recomputed only if it or a neighbour
+            // changed colour in the previous round (the first round computes every vertex).
+            // Colour ids are stable: a splitting class keeps its id for the part whose
+            // signature is unchanged (or, if all of it was recomputed, for the first part in
+            // signature order); the other parts get new ids in signature order.
+            for (int32_t v : cand) {
+                sign(v);
+                seen[v] = round;
             }
-            std::iota(order.begin(), order.end(), 0);
-            std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-                if (sig[a] != sig[b]) return sig[a] < sig[b];
-                return a < b;
+            std::sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+                if (c.col[a] != c.col[b]) return c.col[a] < c.col[b];
+                const int r = cmp(a, b);
+                return r != 0 ? r < 0 : a < b;
             });
-            std::vector<int32_t> nc(n);
-            int32_t k = 0;
-            for (int32_t i = 0; i < n; ++i) {
-                if (i > 0 && sig[order[i]] != sig[order[i - 1]]) ++k;
-                nc[order[i]] = k;
+            // one unchanged member per touched class, signed before any colour moves
+            std::vector<std::pair<int32_t, int32_t>> runs;   // [begin, end) of each class in cand
+            std::vector<int32_t> rep;
+            for (size_t i0 = 0; i0 < cand.size();) {
+                size_t i1 = i0;
+                while (i1 < cand.size() && c.col[cand[i1]] == c.col[cand[i0]]) ++i1;
+                const auto& cell = cells[c.col[cand[i0]]];
+                int32_t r = -1;
+                if (cell.size() > i1 - i0)
+                    for (int32_t v : cell)
+                        if (seen[v] != round) {
+                            r = v;
+                            break;
+                        }
+                if (r >= 0) sign(r);
+                runs.push_back({static_cast<int32_t>(i0), static_cast<int32_t>(i1)});
+                rep.push_back(r);
+                i0 = i1;
             }
-            const int32_t ncol = n ? k + 1 : 0;
-            c.trace.push_back(ncol);
+            changed.clear();
+            for (size_t t = 0; t < runs.size(); ++t) {
+                const int32_t X = c.col[cand[runs[t].first]];
+                const int32_t r = rep[t];
+                for (int32_t i0 = runs[t].first; i0 < runs[t].second;) {
+                    int32_t i1 = i0 + 1;
+                    while (i1 < runs[t].second && cmp(cand[i1], cand[i0]) == 0) ++i1;
+                    // the part keeping X: the unchanged members' signature, else the first part
+                    const bool keep = (r >= 0) ? cmp(cand[i0], r) == 0 : i0 == runs[t].first;
+                    if (!keep) {
+                        const int32_t id = c.ncol++;
+                        cells.emplace_back();
+                        for (int32_t i = i0; i < i1; ++i) {
+                            const int32_t v = cand[i];
+                            auto& from = cells[X];
+                            const int32_t last = from.back();
+                            from[pos[v]] = last;
+                            pos[last] = pos[v];
+                            from.pop_back();
+                            pos[v] = static_cast<int32_t>(cells[id].size());
+                            cells[id].push_back(v);
+                            c.col[v] = id;   // this round's signatures are all computed already
+                            changed.push_back(v);
+                        }
+                    }
+                    i0 = i1;
+                }
+            }
+            c.trace.push_back(c.ncol);
             if (ref && (static_cast<int32_t>(c.trace.size()) > static_cast<int32_t>(ref->size()) ||
-                        (*ref)[c.trace.size() - 1] != ncol))
+                        (*ref)[c.trace.size() - 1] != c.ncol))
                 return false;
-            const bool stable = ncol == c.ncol;
-            c.col.swap(nc);
-            c.ncol = ncol;
-            if (stable) break;
+            if (changed.empty()) break;
+            cand.clear();
+            const int32_t mark = -2 - round;   // fresh marker (seen[] holds rounds >= 0)
+            auto add = [&](int32_t v) {
+                if (seen[v] != mark) {
+                    seen[v] = mark;
+                    cand.push_back(v);
+                }
+            };
+            for (int32_t v : changed) {
+                add(v);
+                for (int64_t j = g_.off[v]; j < g_.off[v + 1]; ++j) add(g_.nbr[j]);
+            }
         }
         if (ref && c.trace.size() != ref->size()) return false;
         return true;
