@@ -230,10 +230,12 @@ def training_measure(Q, torch, W, steps: int = 20) -> dict:
                                               round(float(E.mean()) / g.m, 4)]}
 
 
-def generator_measure(Q, W) -> dict:
+def generator_measure(Q, W, torch) -> dict:
     """Automorphism generators found by the library's search (host) for the 100 x 100 torus,
-    the paper's grid-w-2-100 row, and the edge orbits they give."""
-    import numpy as np
+    the paper's grid-w-2-100 row, and the edge orbits they give; then, as the paper counts
+    it, the speedup of symmetry-reduced evaluation with the search time included over the
+    unreduced evaluation, for cheap terms (C_10000(1,2,5), p = 1) and expensive ones
+    (C_1000(1,2,5), p = 2, cones of 20-22 qubits)."""
     g = W.torus2d(100)
     t0 = time.perf_counter()
     gens, complete = Q.find_generators(g.n, g.edges)
@@ -241,9 +243,48 @@ def generator_measure(Q, W) -> dict:
     pl = Q.Plan(g.n, g.edges, p=1, generators=gens)
     n_orb = pl.info()["n_orbits"]
     pl.close()
-    return {"graph": "torus 100x100 (10000 nodes, 20000 edges)", "seconds": round(dt, 3),
-            "generators": int(len(gens)), "complete": bool(complete), "edge_orbits": int(n_orb),
-            "paper_t_aut_s_context": 58.70}
+    out = {"graph": "torus 100x100 (10000 nodes, 20000 edges)", "seconds": round(dt, 3),
+           "generators": int(len(gens)), "complete": bool(complete), "edge_orbits": int(n_orb),
+           "paper_t_aut_s_context": 58.70}
+
+    def speedup(c, p, P, label):
+        ga, be = W.draw_angles(P, p, 5)
+        gt = torch.tensor(ga, dtype=torch.float64, device="cuda")
+        bt = torch.tensor(be, dtype=torch.float64, device="cuda")
+
+        def unreduced():
+            p_ = Q.Plan(c.n, c.edges, p=p, reduce=False)
+            r = p_.energy_grad(gt, bt)
+            torch.cuda.synchronize()
+            p_.close()
+            return r
+
+        def discovered():
+            gs, _ = Q.find_generators(c.n, c.edges)
+            p_ = Q.Plan(c.n, c.edges, p=p, generators=gs)
+            r = p_.energy_grad(gt, bt)
+            torch.cuda.synchronize()
+            p_.close()
+            return r
+
+        unreduced(), discovered()   # warm-up
+        t0 = time.perf_counter()
+        Eu = unreduced()[0]
+        t_unr = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Er = discovered()[0]
+        t_red = time.perf_counter() - t0
+        return {"graph": label, "unreduced_s": round(t_unr, 4), "search_plus_reduced_s": round(t_red, 4),
+                "speedup": round(t_unr / t_red, 2), "max_abs_dE": float((Eu - Er).abs().max())}
+
+    # cheap terms (p = 1, cones of at most 12 qubits) and expensive ones (p = 2, cones of
+    # 20-22 qubits in device memory); plan and search included in both timings
+    out["discovered_symmetry"] = [
+        speedup(W.circulant(10000, (1, 2, 5)), 1, 64, "C_10000(1,2,5), p=1, 64 points, energy+gradient"),
+        speedup(W.circulant(1000, (1, 2, 5)), 2, 2, "C_1000(1,2,5), p=2, 2 points, energy+gradient"),
+    ]
+    out["paper_median_speedup_context"] = 4.06
+    return out
 
 
 def rqaoa_measure(W) -> dict:
@@ -394,7 +435,7 @@ def main():
         unr.close()
         extra["graph_replay"] = replay_measure(Q, torch, W)
         extra["training"] = training_measure(Q, torch, W)
-        extra["generator_search"] = generator_measure(Q, W)
+        extra["generator_search"] = generator_measure(Q, W, torch)
         try:
             extra["rqaoa"] = rqaoa_measure(W)
         except Exception as ex:   # a contracted graph can outgrow the cone limit

@@ -227,6 +227,28 @@ def test_points_beyond_one_grid(Q):
     assert np.abs(E2.cpu().numpy() - Eo).max() <= ZZ_TOL / 2
 
 
+def test_discovered_generators(Q):
+    # graphs handed over without generators: the library's own search finds them, and the
+    # reduced evaluation with them matches the unreduced one and the oracle
+    rng = np.random.default_rng(4)
+    torus = W.torus2d(8)
+    for g in (W.relabel(torus, rng.permutation(torus.n)), W.circulant(200, (1, 2, 5))):
+        gens, complete = Q.find_generators(g.n, g.edges)
+        assert complete and len(gens) > 0
+        ga, be = W.draw_angles(4, 1, 9)
+        red = Q.Plan(g.n, g.edges, p=1, generators=gens)
+        unr = Q.Plan(g.n, g.edges, p=1, reduce=False)
+        assert red.info()["n_orbits"] < unr.info()["n_orbits"]
+        Er, dgr, dbr = red.energy_grad(dev(ga), dev(be))
+        Eu, dgu, dbu = unr.energy_grad(dev(ga), dev(be))
+        tol = ZZ_TOL * g.m / 2
+        assert (Er - Eu).abs().max().item() <= tol
+        scale = max(dgu.abs().max().item(), dbu.abs().max().item())
+        assert max((dgr - dgu).abs().max().item(), (dbr - dbu).abs().max().item()) <= 1e-4 * scale
+        Eo, _ = oracle.energy(oracle.plan(g.n, g.edges, None, None, 1, reduce=False), ga, be)
+        assert np.abs(Er.cpu().numpy() - Eo).max() <= tol
+
+
 def test_input_errors(Q):
     g = W.random_regular(12, 3, 1)
     pl = Q.Plan(g.n, g.edges, p=2)
