@@ -111,7 +111,7 @@ struct Hz {
     static constexpr int A = 1 << AB;
     static constexpr int W = 1 << (HT - AB);        // threads per tile
     static constexpr int WPE = CF == 0 ? 2 : (CF == 3 ? QAOA_HBM_CF3_WPE : 4);   // minimum waves per SIMD
-    static constexpr uint32_t NPAD = HN + (HN >> 4) + (HN >> 8) + 8 * (HN >> 12);   // padded tile buffer (pad())
+    static constexpr uint32_t NPAD = HN + (HN >> 4) + (HN >> 8) + (AB == 5 ? 2 : 8) * (HN >> 12);   // pad<AB>() buffer
     static constexpr int ROT_IO0 = HT - AB;          // I/O layout of group 0: lanes on tile bits 0..5
     static constexpr int ROT_IOJ = 9 - AB;           // I/O layout of groups >= 1: lanes on tile bits 9..12, 0, 1
 };
@@ -131,32 +131,32 @@ __device__ __forceinline__ uint32_t htbase(uint32_t tau) { return rotl13(tau << 
 
 template <int CF, int RF, int RT, int A>
 __device__ __forceinline__ void hxpose(float2 (&v)[A], float2* xb, uint32_t tau) {
-    float2* pf = xb + opaque_u32(pad(htbase<CF, RF>(tau)));
-    const float2* pt = xb + opaque_u32(pad(htbase<CF, RT>(tau)));
+    float2* pf = xb + opaque_u32(pad<Hz<CF>::AB>(htbase<CF, RF>(tau)));
+    const float2* pt = xb + opaque_u32(pad<Hz<CF>::AB>(htbase<CF, RT>(tau)));
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) pf[pad(hroff<CF, RF>(r))] = v[r];
+    for (int r = 0; r < A; ++r) pf[pad<Hz<CF>::AB>(hroff<CF, RF>(r))] = v[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < A; ++r) v[r] = pt[pad(hroff<CF, RT>(r))];
+    for (int r = 0; r < A; ++r) v[r] = pt[pad<Hz<CF>::AB>(hroff<CF, RT>(r))];
 }
 
 // psi and lambda through two LDS buffers at once (one barrier pair instead of two).
 template <int CF, int RF, int RT, int A>
 __device__ __forceinline__ void hxpose_dual(float2 (&f)[A], float2 (&l)[A], float2* xa, float2* xc, uint32_t tau) {
-    const uint32_t of = opaque_u32(pad(htbase<CF, RF>(tau)));
-    const uint32_t ot = opaque_u32(pad(htbase<CF, RT>(tau)));
+    const uint32_t of = opaque_u32(pad<Hz<CF>::AB>(htbase<CF, RF>(tau)));
+    const uint32_t ot = opaque_u32(pad<Hz<CF>::AB>(htbase<CF, RT>(tau)));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        xa[of + pad(hroff<CF, RF>(r))] = f[r];
-        xc[of + pad(hroff<CF, RF>(r))] = l[r];
+        xa[of + pad<Hz<CF>::AB>(hroff<CF, RF>(r))] = f[r];
+        xc[of + pad<Hz<CF>::AB>(hroff<CF, RF>(r))] = l[r];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < A; ++r) {
-        f[r] = xa[ot + pad(hroff<CF, RT>(r))];
-        l[r] = xc[ot + pad(hroff<CF, RT>(r))];
+        f[r] = xa[ot + pad<Hz<CF>::AB>(hroff<CF, RT>(r))];
+        l[r] = xc[ot + pad<Hz<CF>::AB>(hroff<CF, RT>(r))];
     }
 }
 
