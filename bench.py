@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "0097d27763273488efe85dc53f9282811bf3edd72fef5b102dc693246a02696e",
+HBM_TRAFFIC = {"sources_sha256": "5ad626be8b3afac07145ac9bc8c87f5c0b6d0333fd7c1f6d589ea4d5a3139796",
                "counted_over_algorithmic": 1.005}
 
 
