@@ -76,8 +76,10 @@ typedef struct {
 
 /* Planning options.  Pass NULL for the defaults (qaoa_plan_opts_default). */
 typedef struct {
-    int64_t mem_budget_bytes;     /* device bytes the plan may use for cone states;
-                                     0 = 85 % of free device memory at first use */
+    int64_t mem_budget_bytes;     /* device bytes the plan may use for cone states held in
+                                     device memory; 0 = 85 % of free device memory at first
+                                     use.  Items are batched within it, at most as many per
+                                     batch as give 2^17 workgroups per pass */
     int32_t reduce;               /* 1 = one term per edge orbit (default); 0 = every edge is
                                      its own term (the plain, unreduced light-cone sum) */
     int32_t max_cone_qubits;      /* 0 = 30 */
