@@ -42,7 +42,8 @@ extern "C" {
 typedef int32_t qaoa_status;
 enum {
     QAOA_OK = 0,
-    QAOA_EINVAL = -1,   /* bad sizes or ids, self-loop, duplicate edge, p < 1, n_points < 1,
+    QAOA_EINVAL = -1,   /* bad sizes or ids, self-loop, duplicate edge, p outside [1, 1024],
+                           n_points outside [1, 2^30],
                            weights without a common unit (the GPU path counts cut values in it) */
     QAOA_ENOTAUT = -2,  /* a generator is not a weight-preserving automorphism */
     QAOA_ECONE = -3,    /* a light cone exceeds max_cone_qubits, or its cut range exceeds 255 */
@@ -71,7 +72,7 @@ typedef struct {
     int32_t n_generators;         /* >= 0 */
     const int32_t* generators;    /* row-major [n_generators][n_nodes]: image of node i under
                                      generator g; NULL / 0 = trivial group */
-    int32_t p;                    /* QAOA depth >= 1 */
+    int32_t p;                    /* QAOA depth, 1 <= p <= 1024 */
 } qaoa_problem;
 
 /* Planning options.  Pass NULL for the defaults (qaoa_plan_opts_default). */
@@ -114,25 +115,38 @@ typedef struct {
     int64_t graph_replays;        /* energy calls served by replaying a captured graph */
     double weight_unit;           /* delta: every weight is an integer multiple of it (1 for
                                      integer weights); cut values are counted in this unit */
+    int64_t pass_launches[10];    /* launches of each device-memory pass kind in the last eagerly
+                                     run energy call (all batches), indexed by kind:
+                                     0 generate + layer-1 mixer, 1 p = 1 single pass, 2 mixer only,
+                                     3 mixer + phase + mixer across a layer boundary, 4 final pass,
+                                     5 p = 1 forward + adjoint, 6 final pass + adjoint turn,
+                                     7 undo of 0, 8 undo of 2, 9 undo of 3 */
 } qaoa_plan_info;
 
 void qaoa_plan_opts_default(qaoa_plan_opts* opts);
 
 /* Build a plan: canonicalise the edges (u < v), verify every generator (a permutation of
- * the nodes mapping E onto E and keeping each weight bit for bit), form edge orbits
- * (representative = smallest edge index, orbits numbered by ascending representative),
- * and extract one light cone per orbit: qubit 0 = u, qubit 1 = v, the rest of the
- * radius-p ball by (distance, node id); every induced edge is a cone edge.
+ * the nodes mapping E onto E and keeping each weight bit for bit: an automorphism of the
+ * edge-coloured graph, Sec. 2.6 and Sec. 4), form edge orbits under the group they
+ * generate (Sec. 3, Theorem 1: terms of one orbit have equal expectation; representative =
+ * smallest edge index, orbits numbered by ascending representative), and extract one
+ * light cone per orbit (Sec. 2.3, the reverse causal cone of Z_u Z_v after p layers):
+ * qubit 0 = u, qubit 1 = v, the rest of the radius-p ball by (distance, node id); every
+ * induced edge is a cone edge.
  * Host-only work; device tables are built on the first energy call.
  * Errors: EINVAL, ENOTAUT, ECONE. */
 qaoa_status qaoa_plan_lightcones(const qaoa_problem* problem, const qaoa_plan_opts* opts,
                                  qaoa_plan_t* out);
 
-/* Summary of a plan (host). */
+/* Summary of a plan (host): sizes of the reduced problem of Sec. 3 (number of orbits M,
+ * the cone-size histogram of Sec. 2.3) and device bookkeeping.  out is caller-owned.
+ * Errors: EINVAL (NULL argument). */
 qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out);
 
-/* Orbit assignment (host buffers): edge_orbit[n_edges], orbit_rep[n_orbits],
- * orbit_size[n_orbits].  Any pointer may be NULL. */
+/* Orbit assignment of Sec. 3 (the classes S~_m of equivalent terms and their chosen
+ * representatives) into caller-owned host buffers: edge_orbit[n_edges] (orbit of each edge,
+ * input order), orbit_rep[n_orbits] (representative edge index), orbit_size[n_orbits]
+ * (edges in the orbit).  Any pointer may be NULL.  Errors: EINVAL (NULL plan). */
 qaoa_status qaoa_plan_orbits(qaoa_plan_t plan, int32_t* edge_orbit, int64_t* orbit_rep,
                              int64_t* orbit_size);
 
@@ -150,12 +164,29 @@ qaoa_status qaoa_energy(qaoa_plan_t plan, int64_t n_points, const double* gamma,
                         const double* beta, double* energy, double* term_zz,
                         qaoa_stream_t stream);
 
-/* Energy and its gradient dE/dgamma_l, dE/dbeta_l (device [n_points * p] each) by an
- * adjoint sweep that recovers the forward state by applying inverse layers.
+/* Energy (as qaoa_energy) and its gradient dE/dgamma_l, dE/dbeta_l (device [n_points * p]
+ * each, same layout as the angles).  The paper evaluates energies only; training the
+ * angles (Sec. 2.2: the angles are optimised classically) needs the gradient, computed
+ * here term by term on the same light cones by an adjoint sweep: lambda = Z_u Z_v psi is
+ * carried back through the inverse layers, and d<Z_u Z_v>/dbeta_l = 2 Im <lambda|sum_j X_j|psi>,
+ * d<Z_u Z_v>/dgamma_l = 2 Im <lambda|H|psi> at layer l.  The forward state is recovered by
+ * applying inverse layers (checkpoint_mode 0) or read back from states stored during the
+ * forward sweep (see qaoa_plan_opts.checkpoint_mode).
  * Errors: EINVAL, ENOMEM, EHIP. */
 qaoa_status qaoa_energy_grad(qaoa_plan_t plan, int64_t n_points, const double* gamma,
                              const double* beta, double* energy, double* dgamma,
                              double* dbeta, qaoa_stream_t stream);
+
+/* qaoa_energy_grad that also returns the per-orbit terms: term_zz as in qaoa_energy, and
+ * term_grad: device [n_points * 2p * n_orbits] (point-major, then parameter, then orbit:
+ * term_grad[(i * 2p + j) * n_orbits + m] = d zz_m / d gamma_(j+1) for j < p and
+ * d zz_m / d beta_(j-p+1) for j >= p, in radians; the energy gradient is
+ * -1/2 sum_m W_m term_grad[..][m], Sec. 3 reduced sum).  Either pointer may be NULL.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+qaoa_status qaoa_energy_grad_terms(qaoa_plan_t plan, int64_t n_points, const double* gamma,
+                                   const double* beta, double* energy, double* dgamma,
+                                   double* dbeta, double* term_zz, double* term_grad,
+                                   qaoa_stream_t stream);
 
 /* Diagnostics for plans built with opts.profile = 1: per kernel group of the last energy
  * call (one group per cone size k, plus the table and combine kernels, reported with
@@ -166,7 +197,6 @@ qaoa_status qaoa_energy_grad(qaoa_plan_t plan, int64_t n_points, const double* g
 qaoa_status qaoa_plan_kernel_times(qaoa_plan_t plan, int32_t cap, int32_t* k_out, int64_t* items_out,
                                    double* ms_out, int32_t* n_out);
 
-/* Release the plan and everything it owns on the device (synchronises the device). */
 /* Automorphism generators of the problem's graph (edge weights act as edge colours), for
  * graphs whose symmetry group is not known by construction; the paper obtains its group
  * from an automorphism solver (Sec. 2.6, Sec. 5).  Colour refinement and
@@ -183,6 +213,7 @@ qaoa_status qaoa_plan_kernel_times(qaoa_plan_t plan, int32_t cap, int32_t* k_out
 qaoa_status qaoa_find_generators(const qaoa_problem* pr, int32_t max_generators, double time_limit_s,
                                  int32_t* generators, int32_t* n_found, int32_t* complete);
 
+/* Release the plan and everything it owns on the device (synchronises the device). */
 void qaoa_plan_destroy(qaoa_plan_t plan);
 
 /* Text of the last failure on this thread ("" if none). */

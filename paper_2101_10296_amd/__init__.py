@@ -86,8 +86,9 @@ class Plan:
     def info(self) -> dict:
         inf = _capi.PlanInfo()
         _check(_capi.lib().qaoa_plan_query(self._h, C.byref(inf)))
-        d = {f: getattr(inf, f) for f, _ in _capi.PlanInfo._fields_ if f != "k_hist"}
+        d = {f: getattr(inf, f) for f, _ in _capi.PlanInfo._fields_ if f not in ("k_hist", "pass_launches")}
         d["k_hist"] = list(inf.k_hist)
+        d["pass_launches"] = list(inf.pass_launches)
         return d
 
     def orbits(self):
@@ -176,6 +177,24 @@ class Plan:
         _check(_capi.lib().qaoa_energy_grad(self._h, P, g.data_ptr(), b.data_ptr(), E.data_ptr(),
                                             dg.data_ptr(), db.data_ptr(), stream))
         return E, dg, db
+
+    def energy_grad_terms(self, gamma, beta):
+        """(E [P], dE/dgamma [P, p], dE/dbeta [P, p], zz [P, M], d zz / d(gamma, beta) [P, 2p, M]):
+        the energy gradient together with every orbit term and its own gradient."""
+        import torch
+        g, b = self._angles(gamma, beta)
+        P = g.shape[0]
+        dev = g.device
+        M = max(self.n_orbits, 1)
+        E = torch.empty((P,), dtype=torch.float64, device=dev)
+        dg = torch.empty((P, self.p), dtype=torch.float64, device=dev)
+        db = torch.empty((P, self.p), dtype=torch.float64, device=dev)
+        zz = torch.empty((P, M), dtype=torch.float64, device=dev)
+        tg = torch.empty((P, 2 * self.p, M), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(_capi.lib().qaoa_energy_grad_terms(self._h, P, g.data_ptr(), b.data_ptr(), E.data_ptr(), dg.data_ptr(),
+                                                  db.data_ptr(), zz.data_ptr(), tg.data_ptr(), stream))
+        return E, dg, db, zz[:, : self.n_orbits], tg[:, :, : self.n_orbits]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -30,7 +30,8 @@ class PlanInfo(C.Structure):
                 ("min_k", C.c_int32), ("max_k", C.c_int32), ("k_hist", C.c_int64 * 31),
                 ("total_weight", C.c_double), ("cut_min", C.c_int32), ("cut_max", C.c_int32),
                 ("n_hbm_cones", C.c_int64), ("device_bytes", C.c_int64),
-                ("graph_replays", C.c_int64), ("weight_unit", C.c_double)]
+                ("graph_replays", C.c_int64), ("weight_unit", C.c_double),
+                ("pass_launches", C.c_int64 * 10)]
 
 
 _lib = None
@@ -58,6 +59,8 @@ def lib():
         L.qaoa_energy.restype = i32
         L.qaoa_energy_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.qaoa_energy_grad.restype = i32
+        L.qaoa_energy_grad_terms.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.qaoa_energy_grad_terms.restype = i32
         L.qaoa_plan_kernel_times.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(C.c_double),
                                              C.POINTER(i32)]
         L.qaoa_plan_kernel_times.restype = i32

@@ -108,11 +108,34 @@ hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_
     return hipSuccess;
 }
 
+// g[i][j][m] *= delta for j < p: per-term gamma derivatives from cut values counted in the
+// weight unit delta to radians (only when the caller asks for the per-term gradient).
+__global__ void k_scale_gamma_terms(double* __restrict__ g, int64_t P, int32_t p, int32_t M, double delta) {
+    const int64_t total = P * p * static_cast<int64_t>(M);
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t i = t / (static_cast<int64_t>(p) * M);
+        const int64_t r = t - i * p * static_cast<int64_t>(M);
+        g[(i * 2 * p) * static_cast<int64_t>(M) + r] *= delta;
+    }
+}
+
+hipError_t launch_scale_gamma_terms(double* g, int64_t P, int32_t p, int32_t M, double delta, hipStream_t st) {
+    const int64_t total = P * p * static_cast<int64_t>(M);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_gamma_terms, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g, P, p, M, delta);
+    return hipGetLastError();
+}
+
+int64_t combine_chunk(uint32_t ny) { return static_cast<int64_t>(UINT32_MAX) / (256 * static_cast<int64_t>(ny)); }
+
 hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
                           double delta, double* energy, double* dgamma, double* dbeta, hipStream_t st) {
     const unsigned ny = (g != nullptr) ? static_cast<unsigned>(1 + 2 * p) : 1u;
-    // one block per point; a grid holds fewer than 2^32 threads
-    constexpr int64_t CH = static_cast<int64_t>(UINT32_MAX) / 256;
+    // one block per (point, value); a grid holds fewer than 2^32 threads
+    const int64_t CH = combine_chunk(ny);
     for (int64_t i0 = 0; i0 < P; i0 += CH) {
         const unsigned nx = static_cast<unsigned>(P - i0 < CH ? P - i0 : CH);
         hipLaunchKernelGGL(k_combine, dim3(nx, ny), dim3(256), 0, st, W, zz, g, M, p, delta, i0, energy, dgamma,

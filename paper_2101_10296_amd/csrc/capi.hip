@@ -20,6 +20,11 @@ qaoa_status set_err(qaoa_status st, const std::string& msg) {
 }
 }  // namespace
 
+namespace qaoa {
+qaoa_status set_last_error(qaoa_status st, const std::string& msg) { return set_err(st, msg); }
+void clear_last_error() { g_last_error.clear(); }
+}  // namespace qaoa
+
 extern "C" {
 
 void qaoa_plan_opts_default(qaoa_plan_opts* o) {
@@ -119,6 +124,7 @@ qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
     out->device_bytes = static_cast<int64_t>(plan->resident_bytes);
     out->graph_replays = plan->graph_replays;
     out->weight_unit = plan->hp.delta;
+    for (int i = 0; i < 10 && i < qaoa::N_PASS_KINDS; ++i) out->pass_launches[i] = plan->pass_launches[i];
     return QAOA_OK;
 }
 
@@ -148,7 +154,7 @@ qaoa_status qaoa_energy(qaoa_plan_t plan, int64_t n_points, const double* gamma,
     if (n_points < 1 || n_points > (int64_t{1} << 30)) return set_err(QAOA_EINVAL, "n_points must be in [1, 2^30]");
     if (!gamma || !beta || !energy) return set_err(QAOA_EINVAL, "gamma, beta and energy must be device pointers");
     std::string msg;
-    const qaoa_status st = qaoa::run_energy(plan, n_points, gamma, beta, energy, term_zz, nullptr, nullptr,
+    const qaoa_status st = qaoa::run_energy(plan, n_points, gamma, beta, energy, term_zz, nullptr, nullptr, nullptr,
                                             reinterpret_cast<hipStream_t>(stream), msg);
     if (st != QAOA_OK) return set_err(st, msg);
     g_last_error.clear();
@@ -162,7 +168,22 @@ qaoa_status qaoa_energy_grad(qaoa_plan_t plan, int64_t n_points, const double* g
     if (!gamma || !beta || !energy || !dgamma || !dbeta)
         return set_err(QAOA_EINVAL, "gamma, beta, energy, dgamma and dbeta must be device pointers");
     std::string msg;
-    const qaoa_status st = qaoa::run_energy(plan, n_points, gamma, beta, energy, nullptr, dgamma, dbeta,
+    const qaoa_status st = qaoa::run_energy(plan, n_points, gamma, beta, energy, nullptr, dgamma, dbeta, nullptr,
+                                            reinterpret_cast<hipStream_t>(stream), msg);
+    if (st != QAOA_OK) return set_err(st, msg);
+    g_last_error.clear();
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_energy_grad_terms(qaoa_plan_t plan, int64_t n_points, const double* gamma, const double* beta,
+                                   double* energy, double* dgamma, double* dbeta, double* term_zz,
+                                   double* term_grad, qaoa_stream_t stream) {
+    if (!plan) return set_err(QAOA_EINVAL, "plan is NULL");
+    if (n_points < 1 || n_points > (int64_t{1} << 30)) return set_err(QAOA_EINVAL, "n_points must be in [1, 2^30]");
+    if (!gamma || !beta || !energy || !dgamma || !dbeta)
+        return set_err(QAOA_EINVAL, "gamma, beta, energy, dgamma and dbeta must be device pointers");
+    std::string msg;
+    const qaoa_status st = qaoa::run_energy(plan, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, term_grad,
                                             reinterpret_cast<hipStream_t>(stream), msg);
     if (st != QAOA_OK) return set_err(st, msg);
     g_last_error.clear();

@@ -26,7 +26,7 @@ struct EvalArgs {
     int32_t M;              // terms (orbits)
     int32_t R;              // phase-table row length (global cut range + 1)
     const float2* phase;    // [P][p][R]: exp(-i gamma_l c), c = plan.cut_min + index
-    const float2* mix;      // [P][p]: (cos beta_l, sin beta_l)
+    const float2* mix;      // [P][p]: (tau_l, |kappa_l|^2) of the factored mixer exp(-i beta_l X)
     double* zz;             // [P][M]
     double* g;              // [P][2p][M]: d zz / d gamma_l (l < p), d zz / d beta_l (p <= l < 2p)
 };

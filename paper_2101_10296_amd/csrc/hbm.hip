@@ -132,9 +132,16 @@ hipError_t launch_fill_zero(double* x, int64_t n, hipStream_t st) {
 
 hipError_t launch_tile_reduce(const ConeHbm* cones, const double* gpart, int64_t item0, int64_t n_batch,
                               int64_t tiles, int32_t stride, int32_t nvals, const EvalArgs& ea, hipStream_t st) {
-    hipLaunchKernelGGL(k_tile_reduce, dim3(static_cast<unsigned>(n_batch), static_cast<unsigned>(nvals)), dim3(256),
-                       0, st, cones, gpart, item0, tiles, stride, ea);
-    return hipGetLastError();
+    // one block per (item, value); a grid holds fewer than 2^32 work-items
+    const int64_t CH = static_cast<int64_t>(UINT32_MAX) / (256 * static_cast<int64_t>(nvals));
+    for (int64_t b0 = 0; b0 < n_batch; b0 += CH) {
+        const unsigned nx = static_cast<unsigned>(n_batch - b0 < CH ? n_batch - b0 : CH);
+        hipLaunchKernelGGL(k_tile_reduce, dim3(nx, static_cast<unsigned>(nvals)), dim3(256), 0, st, cones,
+                           gpart + static_cast<size_t>(b0) * tiles * stride, item0 + b0, tiles, stride, ea);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace qaoa

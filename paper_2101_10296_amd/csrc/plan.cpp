@@ -135,6 +135,7 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
     if (m < 0) fail(kEINVAL, "n_edges must be >= 0");
     if (m > 0 && (!eu || !ev)) fail(kEINVAL, "edge arrays are NULL");
     if (p < 1) fail(kEINVAL, "p must be >= 1");
+    if (p > 1024) fail(kEINVAL, "p must be <= 1024 (launch grids carry 2p + 1 values per point)");
     if (n_gen < 0 || (n_gen > 0 && !gens)) fail(kEINVAL, "bad generator array");
     if (opt.max_cone_qubits < 2 || opt.max_cone_qubits > 30) fail(kEINVAL, "max_cone_qubits must be in [2, 30]");
     if (opt.k_lds_max != 14) fail(kEINVAL, "k_lds_max must be 14 (cones above it are kept in device memory)");

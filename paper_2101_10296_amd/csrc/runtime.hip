@@ -290,7 +290,8 @@ namespace {
 // The launch sequence of one energy call.  With fixed_batches the HBM groups reuse the
 // batch sizes of the previous call (and so allocate nothing): used while capturing.
 qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const double* beta, double* energy,
-                    double* term_zz, double* dgamma, double* dbeta, hipStream_t stream, bool fixed_batches,
+                    double* term_zz, double* dgamma, double* dbeta, double* term_grad, hipStream_t stream,
+                    bool fixed_batches,
                     std::string& msg) {
     qaoa_status st = ensure_device(P, msg);
     if (st != QAOA_OK) return st;
@@ -308,7 +309,9 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         zz = P->d_zz;
     }
     double* g = nullptr;
-    if (grad) {
+    if (grad && term_grad) {
+        g = term_grad;
+    } else if (grad) {
         if ((st = grow(P->d_g, P->cap_g, static_cast<size_t>(n_points) * 2 * p * M, msg)) != QAOA_OK) return st;
         g = P->d_g;
     }
@@ -331,7 +334,10 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         QCHECK(tm.end());
     }
     // ---- HBM-resident cones: batches of items through the pass program
-    if (!fixed_batches) P->hbm_batch.assign(P->hbm_groups.size(), 0);
+    if (!fixed_batches) {
+        P->hbm_batch.assign(P->hbm_groups.size(), 0);
+        std::fill(std::begin(P->pass_launches), std::end(P->pass_launches), int64_t{0});
+    }
     for (size_t gi = 0; gi < P->hbm_groups.size(); ++gi) {
         const auto& grp = P->hbm_groups[gi];
         const int k = grp.K, kh = k - 1;      // stored qubits: the half with qubit k-1 = 0
@@ -417,13 +423,20 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
                 pa.tpw = tpw;
                 pa.ea = ea;
                 QCHECK(launch_pass(ps.kind, pa, stream));
+                if (!fixed_batches) P->pass_launches[ps.kind] += 1;
             }
             QCHECK(launch_tile_reduce(P->d_hcones + grp.first, P->d_gpart, i0, nb, tiles, stride, nvals, ea, stream));
         }
         QCHECK(tm.end());
     }
     QCHECK(tm.begin(-2, n_points));
-    QCHECK(launch_combine(P->d_W, zz, g, M, p, n_points, hp.delta, energy, dgamma, dbeta, stream));
+    double delta = hp.delta;
+    if (grad && term_grad && delta != 1.0) {
+        // the caller reads the per-term gradient: gamma derivatives in radians
+        QCHECK(launch_scale_gamma_terms(g, n_points, p, M, delta, stream));
+        delta = 1.0;
+    }
+    QCHECK(launch_combine(P->d_W, zz, g, M, p, n_points, delta, energy, dgamma, dbeta, stream));
     QCHECK(tm.end());
     return QAOA_OK;
 }
@@ -437,14 +450,15 @@ void drop_graph(qaoa_plan_s* P) {
 }  // namespace
 
 qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, const double* beta, double* energy,
-                       double* term_zz, double* dgamma, double* dbeta, hipStream_t stream, std::string& msg) {
+                       double* term_zz, double* dgamma, double* dbeta, double* term_grad, hipStream_t stream,
+                       std::string& msg) {
     if (!P->opt.graph)
-        return enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, stream, false, msg);
+        return enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, term_grad, stream, false, msg);
     qaoa_plan_s::GraphKey key;
     key.n_points = n_points;
     key.grad = dgamma != nullptr;
-    const void* ptrs[6] = {gamma, beta, energy, term_zz, dgamma, dbeta};
-    for (int i = 0; i < 6; ++i) key.ptr[i] = ptrs[i];
+    const void* ptrs[7] = {gamma, beta, energy, term_zz, dgamma, dbeta, term_grad};
+    for (int i = 0; i < 7; ++i) key.ptr[i] = ptrs[i];
     if (P->gexec && key == P->gkey) {
         QCHECK(hipGraphLaunch(P->gexec, stream));
         ++P->graph_replays;
@@ -453,11 +467,11 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
     // a new key: run eagerly (allocating what the call needs), then capture the same launch
     // sequence on the plan's own stream; the graph is replayed from the next call on
     drop_graph(P);
-    qaoa_status st = enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, stream, false, msg);
+    qaoa_status st = enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, term_grad, stream, false, msg);
     if (st != QAOA_OK) return st;
     if (!P->cap_stream) QCHECK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
     QCHECK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    st = enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, P->cap_stream, true, msg);
+    st = enqueue(P, n_points, gamma, beta, energy, term_zz, dgamma, dbeta, term_grad, P->cap_stream, true, msg);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(P->cap_stream, &graph);
     if (st == QAOA_OK && ec != hipSuccess) {

@@ -61,15 +61,16 @@ struct qaoa_plan_s {
     float2* d_lam = nullptr;
     double* d_gpart = nullptr;
     std::vector<int64_t> hbm_batch;     // items per batch of each HBM group in the last call
+    int64_t pass_launches[qaoa::N_PASS_KINDS] = {};   // per pass kind, last eager call
 
     // ---- graph replay (opts.graph)
     struct GraphKey {
         int64_t n_points = -1;
         bool grad = false;
-        const void* ptr[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        const void* ptr[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
         bool operator==(const GraphKey& o) const {
             if (n_points != o.n_points || grad != o.grad) return false;
-            for (int i = 0; i < 6; ++i)
+            for (int i = 0; i < 7; ++i)
                 if (ptr[i] != o.ptr[i]) return false;
             return true;
         }
@@ -83,10 +84,15 @@ struct qaoa_plan_s {
 namespace qaoa {
 
 qaoa_status run_energy(qaoa_plan_s* plan, int64_t n_points, const double* gamma, const double* beta,
-                       double* energy, double* term_zz, double* dgamma, double* dbeta, hipStream_t stream,
+                       double* energy, double* term_zz, double* dgamma, double* dbeta, double* term_grad,
+                       hipStream_t stream,
                        std::string& msg);
 
 void release_device(qaoa_plan_s* plan);
+
+// Records msg as this thread's last error (capi.hip) and returns st.
+qaoa_status set_last_error(qaoa_status st, const std::string& msg);
+void clear_last_error();
 qaoa_status kernel_times(qaoa_plan_s* plan, int32_t cap, int32_t* k_out, int64_t* items_out, double* ms_out,
                          int32_t* n_out, std::string& msg);
 
@@ -113,6 +119,9 @@ int hbm_groups_of(int k);
 int hbm_group_qubits(int k, int grp);
 std::vector<PassSpec> hbm_program(int k, int p, bool grad);
 
+hipError_t launch_scale_gamma_terms(double* g, int64_t P, int32_t p, int32_t M, double delta, hipStream_t st);
+// points per k_combine launch with ny blocks per point (grid below 2^32 work-items)
+int64_t combine_chunk(uint32_t ny);
 hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
                           double delta, double* energy, double* dgamma, double* dbeta, hipStream_t st);
 

@@ -5,9 +5,11 @@
   sampled orbit terms against the oracle, the full oracle gradient on five graphs, and
   the energy / gradient consistency of every plan;
 * random 3-regular n=200 at p=3 (300 cones of 20-30 qubits) at its first two angle points
-  (bench.py times the first): the cones the oracle can run (up to 22 qubits) term by term,
-  and for the rest the invariance of energy and gradient under a relabelling of the nodes
-  (which changes every cone's qubit order, so every kernel data path differs).
+  (bench.py times them): every cone of up to 22 qubits term by term against the oracle,
+  stored oracle terms of sampled 24-, 25-, 26- and 28-qubit cones (three pass groups) and
+  stored oracle term gradients of a 24- and a 25-qubit cone; for all of it, the invariance
+  of energy and gradient under a relabelling of the nodes (which changes every cone's qubit
+  order, so every kernel data path differs).
 Tolerances as in test_gpu_parity.py.
 """
 import numpy as np
@@ -27,6 +29,14 @@ def Q():
         pytest.skip("no GPU")
     import paper_2101_10296_amd as Q
     return Q
+
+
+def _golden(kind):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_cases.json")
+    with open(path) as f:
+        return {c["name"]: c for c in json.load(f)[kind]}
 
 
 def _grad_close(dg, db, dgo, dbo, Wt):
@@ -82,10 +92,24 @@ def test_config5ii_full_size(Q):
     info = pl.info()
     assert info["max_k"] == 30 and info["n_hbm_cones"] == 300
     E, zz = pl.energy(dev(ga), dev(be), term_zz=True)
-    E2, dg, db = pl.energy_grad(dev(ga), dev(be))
+    E2, dg, db, zzg, tg = pl.energy_grad_terms(dev(ga), dev(be))
+    assert pl.info()["pass_launches"][8] > 0   # the three-group reverse mixer passes ran
     E, zz, E2 = E.cpu().numpy(), zz.cpu().numpy(), E2.cpu().numpy()
-    dg, db = dg.cpu().numpy(), db.cpu().numpy()
+    dg, db, zzg, tg = dg.cpu().numpy(), db.cpu().numpy(), zzg.cpu().numpy(), tg.cpu().numpy()
     assert np.isfinite(zz).all() and np.abs(zz).max() <= 1 + 1e-5
+    assert np.abs(zzg - zz).max() <= ZZ_TOL
+    # stored oracle values (tests/golden/make_oracle_golden.py) of cones too large to rerun
+    gold = _golden("term_cases")["c5ii_terms_k24_28"]
+    for j, e in enumerate(gold["edges"]):
+        assert pl.cone(e)[0] == gold["k"][j]
+        assert np.abs(zz[:gold["points"], e] - np.array(gold["zz"])[:, j]).max() <= ZZ_TOL, e
+    gold = _golden("term_grad_cases")["c5ii_term_grads_k24_25"]
+    for j, e in enumerate(gold["edges"]):
+        assert pl.cone(e)[0] == gold["k"][j]
+        for i in range(gold["points"]):
+            assert abs(zzg[i, e] - gold["zz"][j][i]) <= ZZ_TOL
+            ref = np.array(gold["dzz"][j][i])
+            assert np.abs(tg[i, :, e] - ref).max() <= 1e-4 * max(np.abs(ref).max(), 1e-3), (e, i)
     np.testing.assert_allclose(E, ((1 - zz) / 2).sum(1), rtol=1e-12, atol=1e-9)
     assert np.abs(E2 - E).max() <= ZZ_TOL * g.m / 2
     # term by term where the oracle can: every cone of at most 22 qubits, at two points

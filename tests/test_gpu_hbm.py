@@ -1,8 +1,11 @@
 """GPU parity of cones held in device memory (more than k_lds_max qubits) against the oracle.
 
-Same tolerances as test_gpu_parity.py.  Covered: two and three pass groups, depths 1-3,
-the p = 1 path that needs no state buffers, the smallest device-memory cones (15 and 16
-qubits: one and two tile pairs), reduced plans and batching under a small memory budget.
+Same tolerances as test_gpu_parity.py.  Covered: one, two and three pass groups of stored
+qubits (a k-qubit cone stores k - 1 qubits: group 0 holds 13, each further group up to 9,
+so three groups start at 24 stored qubits, k = 25), depths 1-5, every pass kind (asserted
+through the plan's per-kind launch counters), the p = 1 path that needs no state buffers,
+the smallest device-memory cones (15 and 16 qubits: one and two tile pairs), reduced plans
+and batching under a small memory budget.
 """
 import numpy as np
 import pytest
@@ -108,19 +111,42 @@ def _golden_cases():
         return {c["name"]: c for c in json.load(f)["cases"]}
 
 
-@pytest.mark.parametrize("name", ["spider5_5_p2", "C60_1_2_3_p3"])
+# pass kinds (index into Plan.info()["pass_launches"])
+FWD_GEN_MIX, FWD_GEN_FINAL, FWD_MIX, FWD_BND_MIX, FWD_BND_FINAL = 0, 1, 2, 3, 4
+GR_GEN_FINAL, GR_BND_FINAL, RV_GEN_MIX, RV_MIX, RV_BND_MIX = 5, 6, 7, 8, 9
+
+# stored case -> (pass kinds of the forward call, pass kinds of the gradient call)
+STORED = {
+    # a 23-qubit cone (22 stored qubits: two pass groups) at p = 2 and 18-20-qubit ones
+    "spider5_5_p2": ({FWD_GEN_MIX, FWD_BND_FINAL}, {FWD_GEN_MIX, GR_BND_FINAL, RV_GEN_MIX}),
+    # 20-22-qubit cones (two groups) at p = 3: the layer-boundary passes in both directions
+    "C60_1_2_3_p3": ({FWD_GEN_MIX, FWD_BND_MIX, FWD_BND_FINAL},
+                     {FWD_GEN_MIX, FWD_BND_MIX, GR_BND_FINAL, RV_BND_MIX, RV_GEN_MIX}),
+    # a 25-qubit cone (24 stored qubits: three groups) at p = 2: the mixer-only passes
+    "spider5_6_p2": ({FWD_GEN_MIX, FWD_MIX, FWD_BND_FINAL}, {FWD_GEN_MIX, FWD_MIX, GR_BND_FINAL, RV_MIX, RV_GEN_MIX}),
+    # four 25-qubit cones at p = 3: every multi-pass kind, both snake directions
+    "spider5_6_p3": ({FWD_GEN_MIX, FWD_MIX, FWD_BND_MIX, FWD_BND_FINAL},
+                     {FWD_GEN_MIX, FWD_MIX, FWD_BND_MIX, GR_BND_FINAL, RV_MIX, RV_BND_MIX, RV_GEN_MIX}),
+}
+
+
+@pytest.mark.parametrize("name", list(STORED))
 def test_stored_oracle_cases(Q, name):
-    # spider5_5_p2: a 23-qubit cone in three pass groups (every pass kind, both snake
-    # directions); C60_1_2_3_p3: 20-22-qubit cones at p = 3.  Oracle values stored by
-    # tests/golden/make_oracle_golden.py.
+    # oracle values stored by tests/golden/make_oracle_golden.py; every term, the energy and
+    # the gradient at every stored point, and the pass kinds that produced them
     c = _golden_cases()[name]
     g = getattr(W, c["family"])(*c["args"])
     ga, be = W.draw_angles(c["points"], c["p"], c["seed"])
     pl = Q.Plan(g.n, g.edges, p=c["p"], generators=g.gens() if c["reduce"] else None, reduce=c["reduce"])
     eo, rep, _ = pl.orbits()
     assert list(rep) == c["rep"]
+    kinds_fwd, kinds_grad = STORED[name]
     E, zz = pl.energy(dev(ga), dev(be), term_zz=True)
+    ran = {i for i, n in enumerate(pl.info()["pass_launches"]) if n}
+    assert ran == kinds_fwd, ran
     E2, dg, db = pl.energy_grad(dev(ga), dev(be))
+    ran = {i for i, n in enumerate(pl.info()["pass_launches"]) if n}
+    assert ran == kinds_grad, ran
     zz = zz.cpu().numpy()
     Wt = float(np.sum(c["W"]))
     assert np.abs(zz - np.array(c["zz"])).max() <= ZZ_TOL

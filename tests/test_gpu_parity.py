@@ -160,17 +160,24 @@ def test_ragged_batches(Q):
 
 
 def test_autograd_function(Q):
+    # the autograd Function's backward, with a weighted upstream gradient, against the
+    # oracle's forward-mode gradient (and the oracle energy for its forward)
     g = W.circulant(40, (1, 2))
     pl = Q.Plan(g.n, g.edges, p=2, generators=g.gens())
     ga, be = W.draw_angles(3, 2, 2)
     gt = dev(ga).requires_grad_(True)
     bt = dev(be).requires_grad_(True)
     E = Q.qaoa_energy(pl, gt, bt)
-    wts = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
-    (E * wts).sum().backward()
-    _, dg, db = pl.energy_grad(dev(ga), dev(be))
-    torch.testing.assert_close(gt.grad, dg * wts[:, None])
-    torch.testing.assert_close(bt.grad, db * wts[:, None])
+    wts = np.array([1.0, -2.0, 0.5])
+    (E * dev(wts)).sum().backward()
+    ref = oracle.plan(g.n, g.edges, None, g.gens(), 2, reduce=True)
+    Eo, dgo, dbo, _ = oracle.energy_grad(ref, ga, be)
+    assert np.abs(E.detach().cpu().numpy() - Eo).max() <= ZZ_TOL * g.m / 2
+    got_g, got_b = gt.grad.cpu().numpy(), bt.grad.cpu().numpy()
+    for i in range(3):
+        want_g, want_b = wts[i] * dgo[i], wts[i] * dbo[i]
+        scale = max(np.abs(want_g).max(), np.abs(want_b).max(), 1e-3 * g.m * abs(wts[i]))
+        assert max(np.abs(got_g[i] - want_g).max(), np.abs(got_b[i] - want_b).max()) <= 1e-4 * scale, i
 
 
 def test_config2_circulant_reduced(Q):
@@ -186,14 +193,64 @@ def test_config3_full_gradient_one_point(Q):
     check_energy(Q, g, p, ga[:1], be[:1], grad=True)
 
 
+def test_config3_gradient_all_points(Q):
+    # the same workload at all 64 angle points against stored oracle energies and gradients
+    # (tests/golden/make_oracle_golden.py), and against FP64 central differences of the
+    # oracle at two of them
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_cases.json")) as f:
+        c = {x["name"]: x for x in json.load(f)["cases"]}["c3_rand3_n1000_p2_all"]
+    (g, p), = W.workload("c3")[0]
+    _, ga, be = W.workload("c3")
+    assert c["points"] == 64 and np.array_equal(W.draw_angles(64, 2, c["seed"])[0], ga)
+    pl = Q.Plan(g.n, g.edges, p=p)
+    E, dg, db = (x.cpu().numpy() for x in pl.energy_grad(dev(ga), dev(be)))
+    Eo, dgo, dbo = np.array(c["energy"]), np.array(c["dgamma"]), np.array(c["dbeta"])
+    assert np.abs(E - Eo).max() <= ZZ_TOL * g.m / 2
+    for i in range(64):
+        ref_inf = max(np.abs(dgo[i]).max(), np.abs(dbo[i]).max())
+        err = max(np.abs(dg[i] - dgo[i]).max(), np.abs(db[i] - dbo[i]).max())
+        assert err <= 1e-4 * max(ref_inf, 1e-3 * g.m), (i, err, ref_inf)
+    # central differences (h = 1e-6) of the oracle energy on a sample of 60 terms, through
+    # the per-term gradients the library returns
+    ref = oracle.plan(g.n, g.edges, None, None, p, reduce=False)
+    ms = np.random.default_rng(30).choice(g.m, size=60, replace=False)
+    sub = dict(ref, cones=[ref["cones"][m] for m in ms], rep=ref["rep"][ms], W=np.ones(len(ms)))
+    fdg, fdb = oracle.energy_fd(sub, ga[:2], be[:2])
+    _, _, _, _, tg = pl.energy_grad_terms(dev(ga[:2]), dev(be[:2]))
+    tg = tg.cpu().numpy()[:, :, ms]
+    got = -0.5 * tg.sum(axis=2)
+    want = np.concatenate([fdg, fdb], axis=1)
+    assert np.abs(got - want).max() <= 1e-4 * max(np.abs(want).max(), 1e-3 * len(ms))
+
+
 def test_config2ii_full_batch_sampled_terms(Q):
     # the bench workload at its full size (15000 cones x 256 points), 40 terms checked
     (g, p), = W.workload("c2ii")[0]
     _, ga, be = W.workload("c2ii")
     pl, E, zz = check_energy(Q, g, p, ga, be, sample=40)
-    E2, dg, db = pl.energy_grad(dev(ga), dev(be))
+    E2, dg, db, zzg, tg = pl.energy_grad_terms(dev(ga), dev(be))
     assert np.abs(E2.cpu().numpy() - E).max() <= ZZ_TOL * g.m / 2
-    assert torch.isfinite(dg).all() and torch.isfinite(db).all()
+    # the full-size gradient call, checked on 40 sampled terms at 16 of its points against
+    # the oracle's forward-mode term gradients; the energy gradient is their orbit-weighted
+    # sum (Sec. 3) over all terms
+    rng = np.random.default_rng(22)
+    ms = rng.choice(g.m, size=40, replace=False)
+    pts = rng.choice(256, size=16, replace=False)
+    ref = oracle.plan(g.n, g.edges, None, None, p, reduce=False)
+    tg_np = tg.cpu().numpy()
+    for m in ms:
+        cone = ref["cones"][m]
+        cut = oracle.cut_values(cone["k"], cone["edges"], cone["weights"])
+        for i in pts:
+            z, dzg, dzb = oracle.zz_and_grad(cone["k"], cut, ga[i], be[i])
+            want = np.concatenate([dzg, dzb])
+            assert abs(zzg[i, m].item() - z) <= ZZ_TOL
+            assert np.abs(tg_np[i, :, m] - want).max() <= 1e-4 * max(np.abs(want).max(), 1e-3), (m, i)
+    want = -0.5 * tg_np.sum(axis=2)
+    got = torch.cat([dg, db], dim=1).cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-9 * g.m
 
 
 def test_batches_beyond_one_grid(Q):

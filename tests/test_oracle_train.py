@@ -1,4 +1,4 @@
-"""Pins of the oracle trainer: Adam ascent reaches known p = 1 optima.
+"""Pins of the oracle trainer: Adam ascent reaches known optima (p = 1, 2, 3).
 
 * a single edge: <C> = (1 + sin 4beta sin gamma) / 2 (the closed form at p = 1), maximal
   value 1 at gamma = pi/2, beta = pi/8;
@@ -30,3 +30,28 @@ def test_ring_reaches_three_quarters():
     # the closed form at that point agrees
     zz = oracle.zz_p1(g.n, g.edges, None, 0, 1, ga[0, 0], be[0, 0])
     assert abs((1 - zz) / 2 - 0.75) < 1e-6
+
+
+def test_ring_p2_reaches_five_sixths():
+    # The ring at depth 2: every edge's cone is a path of six vertices, and the optimum cut
+    # fraction is 5/6 (Farhi, Goldstone and Gutmann's ring values (2p + 1) / (2p + 2)).  The
+    # value is fixed independently of this code; reaching it exercises the layer loop of
+    # both the forward-mode gradient (the trajectory) and the plain statevector (the
+    # returned energy), at p >= 2 where the closed form does not apply.
+    g = W.circulant(12, (1,))
+    pl = oracle.plan(g.n, g.edges, None, g.gens(), 2, reduce=True)
+    assert [c["k"] for c in pl["cones"]] == [6]
+    ga, be, E, hist = oracle.adam_ascent(pl, [[0.5, 0.8], [0.3, 0.6]], [[0.4, 0.2], [0.5, 0.3]], steps=800,
+                                         lr=0.01)
+    assert np.abs(E / g.m - 5 / 6).max() < 1e-7, E / g.m
+    # and on the full ring state, without light cones
+    Eb, _ = oracle.bruteforce_full(g.n, g.edges, None, ga[0], be[0])
+    assert abs(Eb / g.m - 5 / 6) < 1e-7
+
+
+def test_ring_p3_reaches_seven_eighths():
+    g = W.circulant(16, (1,))
+    pl = oracle.plan(g.n, g.edges, None, g.gens(), 3, reduce=True)
+    assert [c["k"] for c in pl["cones"]] == [8]
+    _, _, E, _ = oracle.adam_ascent(pl, [[0.4, 0.8, 1.1]], [[0.5, 0.4, 0.2]], steps=1500, lr=0.01)
+    assert abs(E[0] / g.m - 7 / 8) < 1e-6, E / g.m
