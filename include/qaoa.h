@@ -87,9 +87,17 @@ typedef struct {
     int32_t k_lds_max;            /* cones with k <= this run entirely inside one workgroup,
                                      larger ones as passes over tiles held in device memory
                                      (0 = default; only 14 is accepted) */
-    int32_t checkpoint_mode;      /* adjoint of cones held in HBM: must be 0 = uncompute (the
-                                     forward state is recovered by inverse layers, two live
-                                     states per item); any other value -> QAOA_EINVAL */
+    int32_t checkpoint_mode;      /* adjoint of cones held in device memory (p >= 2):
+                                     0 = uncompute: the forward state is recovered by inverse
+                                         layers, two live states per item (default);
+                                     1 = store: every forward pass but the final one keeps its
+                                         output (one state per pass group and layer), and each
+                                         reverse pass reads the state it needs instead of
+                                         carrying the uncomputed one (c + 1 live states per item,
+                                         c = passes per forward sweep - 1; less traffic, no
+                                         FP32 drift of the uncomputation);
+                                     2 = auto: store where the memory budget holds the extra
+                                         states without fewer items per batch, else uncompute */
     int32_t one_cone_at_a_time;   /* 1 = plain GPU path: one launch per (cone, point) */
     int32_t profile;              /* 1 = record HIP events around every kernel group of each
                                      energy call (read with qaoa_plan_kernel_times) */
@@ -121,6 +129,8 @@ typedef struct {
                                      3 mixer + phase + mixer across a layer boundary, 4 final pass,
                                      5 p = 1 forward + adjoint, 6 final pass + adjoint turn,
                                      7 undo of 0, 8 undo of 2, 9 undo of 3 */
+    int32_t checkpointed_classes; /* device-memory cone-size classes whose adjoint read stored
+                                     forward states in the last eagerly run call */
 } qaoa_plan_info;
 
 void qaoa_plan_opts_default(qaoa_plan_opts* opts);
@@ -187,6 +197,26 @@ qaoa_status qaoa_energy_grad_terms(qaoa_plan_t plan, int64_t n_points, const dou
                                    const double* beta, double* energy, double* dgamma,
                                    double* dbeta, double* term_zz, double* term_grad,
                                    qaoa_stream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid hipMalloc): qaoa_energy_grad with every
+ * per-call buffer (angle tables, per-term values) in a scratch array of
+ * QAOA_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on until the process
+ * ends.  It calls no hipMalloc or hipFree.  Same arguments and results as qaoa_energy_grad;
+ * the points are processed in chunks that fit the array.
+ *   - The plan must already be resident on the current device (its first qaoa_energy or
+ *     qaoa_energy_grad call there uploads its tables) -> else QAOA_EINVAL.
+ *   - Every cone must fit one workgroup (no cone above k_lds_max qubits: larger cones keep
+ *     states of 2^(k-1) * 8 bytes in device memory) -> else QAOA_EINVAL.
+ *   - One point must fit the array: p * (cut range + 1) * 8 + (2p + 1) * n_orbits * 8 bytes
+ *     (plus alignment) <= QAOA_NOALLOC_SCRATCH_BYTES -> else QAOA_EINVAL.
+ *   - All calls on one GPU share its array: calls that overlap on one GPU (other streams or
+ *     threads) race; calls on one stream are ordered by it.
+ * Errors: EINVAL, EHIP. */
+#define QAOA_NOALLOC_SCRATCH_BYTES (32u << 20)
+qaoa_status qaoa_energy_grad_noalloc(qaoa_plan_t plan, int64_t n_points, const double* gamma,
+                                     const double* beta, double* energy, double* dgamma,
+                                     double* dbeta, qaoa_stream_t stream);
 
 /* Diagnostics for plans built with opts.profile = 1: per kernel group of the last energy
  * call (one group per cone size k, plus the table and combine kernels, reported with

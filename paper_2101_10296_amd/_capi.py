@@ -31,7 +31,7 @@ class PlanInfo(C.Structure):
                 ("total_weight", C.c_double), ("cut_min", C.c_int32), ("cut_max", C.c_int32),
                 ("n_hbm_cones", C.c_int64), ("device_bytes", C.c_int64),
                 ("graph_replays", C.c_int64), ("weight_unit", C.c_double),
-                ("pass_launches", C.c_int64 * 10)]
+                ("pass_launches", C.c_int64 * 10), ("checkpointed_classes", C.c_int32)]
 
 
 _lib = None

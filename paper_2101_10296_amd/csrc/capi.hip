@@ -79,9 +79,8 @@ qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* o
         if (o.graph != 0 && o.graph != 1) return set_err(QAOA_EINVAL, "graph must be 0 or 1");
         if (o.graph && (o.profile || o.one_cone_at_a_time))
             return set_err(QAOA_EINVAL, "graph replay cannot be combined with profile or one_cone_at_a_time");
-        if (o.checkpoint_mode != 0)
-            return set_err(QAOA_EINVAL, "checkpoint_mode must be 0: the adjoint recovers forward states by inverse "
-                                        "layers; stored per-pass states are not provided");
+        if (o.checkpoint_mode < 0 || o.checkpoint_mode > 2)
+            return set_err(QAOA_EINVAL, "checkpoint_mode must be 0 (uncompute), 1 (store) or 2 (auto)");
     }
     try {
         auto* plan = new qaoa_plan_s();
@@ -125,6 +124,7 @@ qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
     out->graph_replays = plan->graph_replays;
     out->weight_unit = plan->hp.delta;
     for (int i = 0; i < 10 && i < qaoa::N_PASS_KINDS; ++i) out->pass_launches[i] = plan->pass_launches[i];
+    out->checkpointed_classes = plan->checkpointed_classes;
     return QAOA_OK;
 }
 

@@ -76,8 +76,12 @@ struct PassArgs {
     const int32_t* e_b;
     const int32_t* e_w;
     const uint8_t* tt;         // C_tt tables
-    float2* phi;               // state buffer [batch][2^kh]
+    const float2* phi_in;      // state the pass reads [batch][2^kh] (forward input; for a reverse
+                               // pass the state at the output of the forward pass it undoes)
+    float2* phi;               // state the pass writes [batch][2^kh] (may equal phi_in)
     float2* lam;               // adjoint buffer [batch][2^kh]
+    int32_t store_phi;         // reverse passes: 1 = write the undone psi to phi (uncompute),
+                               // 0 = do not (psi of the next reverse pass is a stored checkpoint)
     double* gpart;             // per (item, tile) partial sums [batch][tiles][2p + 1]
     int64_t item0;             // first item of the batch (item = slot * P + point)
     int32_t n_batch;           // items in the batch
@@ -584,7 +588,7 @@ k_pass(PassArgs pa) {
         }
         if constexpr (KIND == FWD_MIX || KIND == FWD_BND_MIX || KIND == FWD_BND_FINAL || KIND == GR_BND_FINAL) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) load(f[t], pa.phi, off[t], t);
+            for (int t = 0; t < NT; ++t) load(f[t], pa.phi_in, off[t], t);
             const float2 tka = mix0[pa.la - 1];
 #pragma unroll
             for (int t = 0; t < NT; ++t) hmix_group<CF, G0, true, RIO>(f[t], xb, tau, tka.x, pm);   // ends in rotation 0
@@ -690,15 +694,16 @@ k_pass(PassArgs pa) {
             float2 lm[NT][A];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                load(f[t], pa.phi, off[t], t);
+                load(f[t], pa.phi_in, off[t], t);
                 load(lm[t], pa.lam, off[t], t);
             }
             if (pa.fix_layer > 0) {
-                // The first reverse pass reads psi as the forward sweep left it: the final pass
-                // mixed layer p-1 on group 0 (14 qubits with the dropped one) forward but
-                // lambda has undone them, and the factored mixer scales by 1/|kappa| per qubit
-                // in both directions, so psi carries |kappa|^(k-14) where lambda carries
-                // |kappa|^14.
+                // psi read as the forward sweep left it (the first reverse pass, or every reverse
+                // pass reading a stored checkpoint) carries the factored mixer's scale of the
+                // forward direction, 1/|kappa_l| per qubit of the layer l in progress mixed so
+                // far (m of them), where lambda carries 1/|kappa_l| per qubit of that layer
+                // undone (k - m): psi is rescaled by |kappa_l|^(2m - k) (host: fix_pow).  For
+                // the first reverse pass of the uncompute program m = k - 14.
                 const float sc = exp2f(0.5f * pa.fix_pow * log2f(mix0[pa.fix_layer - 1].y));
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
@@ -718,13 +723,17 @@ k_pass(PassArgs pa) {
                 part[0] += 2.0 * static_cast<double>(b);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    if constexpr (DB) {
-                        hxpose_dual<CF, 0, RIO>(f[t], lm[t], xb, xb2, tau);
+                    if (pa.store_phi) {
+                        if constexpr (DB) {
+                            hxpose_dual<CF, 0, RIO>(f[t], lm[t], xb, xb2, tau);
+                        } else {
+                            hxpose<CF, 0, RIO>(f[t], xb, tau);
+                            hxpose<CF, 0, RIO>(lm[t], xb, tau);
+                        }
+                        store(f[t], pa.phi, off[t], t);
                     } else {
-                        hxpose<CF, 0, RIO>(f[t], xb, tau);
                         hxpose<CF, 0, RIO>(lm[t], xb, tau);
                     }
-                    store(f[t], pa.phi, off[t], t);
                     store(lm[t], pa.lam, off[t], t);
                 }
             } else {
@@ -764,13 +773,17 @@ k_pass(PassArgs pa) {
                     part[2] += 2.0 * static_cast<double>(ba);
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
-                        if constexpr (DB) {
-                            hxpose_dual<CF, RL, RIO>(f[t], lm[t], xb, xb2, tau);
+                        if (pa.store_phi) {
+                            if constexpr (DB) {
+                                hxpose_dual<CF, RL, RIO>(f[t], lm[t], xb, xb2, tau);
+                            } else {
+                                hxpose<CF, RL, RIO>(f[t], xb, tau);
+                                hxpose<CF, RL, RIO>(lm[t], xb, tau);
+                            }
+                            store(f[t], pa.phi, off[t], t);
                         } else {
-                            hxpose<CF, RL, RIO>(f[t], xb, tau);
                             hxpose<CF, RL, RIO>(lm[t], xb, tau);
                         }
-                        store(f[t], pa.phi, off[t], t);
                         store(lm[t], pa.lam, off[t], t);
                     }
                 }

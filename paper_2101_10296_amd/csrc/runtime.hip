@@ -60,29 +60,53 @@ int hbm_group_qubits(int k, int grp) {
     return std::min(k, lo + 9) - lo;
 }
 
+int hbm_checkpoints(int k, int p) {
+    return p == 1 ? 0 : 1 + (p - 1) * (hbm_groups_of(k - 1) - 1) - 1;
+}
+
 // Forward program over the stored qubits (kh = k - 1): layer l (1 <= l <= p-1) visits the
 // groups in descending order when p-1-l is even, ascending otherwise, so layer p-1 ends on
 // group 0 and consecutive layers share a pass.  Group-0 passes also mix the dropped qubit
 // k-1 (14 qubits per layer).  With grad, the last pass is the fused final/adjoint pass and
 // the earlier passes follow in reverse as RV_* passes; m0a / m0b count the qubits of a
 // layer already undone by earlier reverse passes.
-std::vector<PassSpec> hbm_program(int k, int p, bool grad) {
+std::vector<PassSpec> hbm_program(int k, int p, bool grad, bool ckpt) {
     std::vector<PassSpec> fwd;
     const int kh = k - 1;
     const int n = hbm_groups_of(kh);
     auto layer_qubits = [&](int g) { return hbm_group_qubits(kh, g) + (g == 0 ? 1 : 0); };
     if (p == 1) {
-        fwd.push_back({grad ? GR_GEN_FINAL : FWD_GEN_FINAL, 0, 0, 1, 0, 0, 0, 0});
+        fwd.push_back({grad ? GR_GEN_FINAL : FWD_GEN_FINAL, 0, 0, 1, 0, 0});
         return fwd;
     }
+    ckpt = ckpt && grad;
     auto group_at = [&](int l, int j) { return (((p - 1 - l) & 1) == 0) ? n - 1 - j : j; };
-    fwd.push_back({FWD_GEN_MIX, group_at(1, 0), 0, 1, 0, 0, 0, 0});
+    // in_prog[i] / mixed[i]: the layer in progress after forward pass i and how many of its
+    // qubits have been mixed by then (the forward scale of the state written by pass i)
+    std::vector<int> in_prog, mixed;
+    fwd.push_back({FWD_GEN_MIX, group_at(1, 0), 0, 1, 0, 0});
+    in_prog.push_back(1);
+    mixed.push_back(layer_qubits(fwd.back().group));
     for (int l = 1; l <= p - 1; ++l)
         for (int j = 1; j < n; ++j) {
             const int g = group_at(l, j);
-            if (j < n - 1) fwd.push_back({FWD_MIX, g, l, 0, 0, 0, 0, 0});
-            else if (l + 1 <= p - 1) fwd.push_back({FWD_BND_MIX, g, l, l + 1, 0, 0, 0, 0});
-            else fwd.push_back({FWD_BND_FINAL, g, l, p, 0, 0, 0, 0});
+            if (j < n - 1) {
+                fwd.push_back({FWD_MIX, g, l, 0, 0, 0});
+                in_prog.push_back(l);
+                mixed.push_back(mixed.back() + layer_qubits(g));
+            } else if (l + 1 <= p - 1) {
+                fwd.push_back({FWD_BND_MIX, g, l, l + 1, 0, 0});
+                in_prog.push_back(l + 1);
+                mixed.push_back(layer_qubits(g));
+            } else {
+                fwd.push_back({FWD_BND_FINAL, g, l, p, 0, 0});
+            }
+        }
+    const int nf = static_cast<int>(fwd.size()) - 1;   // forward passes before the final one
+    if (ckpt)
+        for (int i = 0; i <= nf; ++i) {
+            fwd[i].ck_in = i - 1;
+            fwd[i].ck_out = i < nf ? i : -1;
         }
     if (!grad) return fwd;
     std::vector<PassSpec> out(fwd.begin(), fwd.end() - 1);
@@ -92,7 +116,7 @@ std::vector<PassSpec> hbm_program(int k, int p, bool grad) {
     fin.m0a = undone[fin.la];
     undone[fin.la] += layer_qubits(fin.group);
     out.push_back(fin);
-    for (int i = static_cast<int>(fwd.size()) - 2; i >= 0; --i) {
+    for (int i = nf - 1; i >= 0; --i) {
         PassSpec r = fwd[i];
         const int h = layer_qubits(r.group);
         if (r.kind == FWD_GEN_MIX) {
@@ -110,9 +134,16 @@ std::vector<PassSpec> hbm_program(int k, int p, bool grad) {
             r.m0a = undone[r.la];
             undone[r.la] += h;
         }
-        if (i == static_cast<int>(fwd.size()) - 2) {
-            r.fix_layer = fin.la;
-            r.fix_pow = k - 2 * layer_qubits(0);
+        if (ckpt || i == nf - 1) {
+            // psi read as the forward sweep left it (pass i's output): rescale it from the
+            // forward scale of its layer in progress to lambda's
+            r.fix_layer = in_prog[i];
+            r.fix_pow = 2 * mixed[i] - k;
+        }
+        if (ckpt) {
+            r.ck_in = i;
+            r.ck_out = -1;
+            r.store_phi = 0;
         }
         out.push_back(r);
     }
@@ -336,7 +367,9 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
     // ---- HBM-resident cones: batches of items through the pass program
     if (!fixed_batches) {
         P->hbm_batch.assign(P->hbm_groups.size(), 0);
+        P->hbm_ckpt.assign(P->hbm_groups.size(), 0);
         std::fill(std::begin(P->pass_launches), std::end(P->pass_launches), int64_t{0});
+        P->checkpointed_classes = 0;
     }
     for (size_t gi = 0; gi < P->hbm_groups.size(); ++gi) {
         const auto& grp = P->hbm_groups[gi];
@@ -348,39 +381,56 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         const bool need_phi = p >= 2;
         const bool need_lam = grad && p >= 2;
         const size_t state_bytes = (size_t{1} << kh) * sizeof(float2);
-        const size_t per_item = (need_phi ? state_bytes : 0) + (need_lam ? state_bytes : 0) +
-                                static_cast<size_t>(tiles) * stride * sizeof(double);
+        const size_t gpart_bytes = static_cast<size_t>(tiles) * stride * sizeof(double);
+        // checkpoints: every forward pass but the final one keeps its output (nck states)
+        const int nck = hbm_checkpoints(k, p);
+        const size_t per_unc = (need_phi ? state_bytes : 0) + (need_lam ? state_bytes : 0) + gpart_bytes;
+        const size_t per_ck = static_cast<size_t>(nck) * state_bytes + state_bytes + gpart_bytes;
         size_t budget = static_cast<size_t>(P->opt.mem_budget_bytes);
-        if (fixed_batches) {
-            budget = per_item * static_cast<size_t>(P->hbm_batch[gi]);
-        } else if (budget == 0) {
+        if (!fixed_batches && budget == 0) {
             size_t fr = 0, tot = 0;
             QCHECK(hipMemGetInfo(&fr, &tot));
             const size_t held = P->cap_phi * sizeof(float2) + P->cap_lam * sizeof(float2) + P->cap_gpart * sizeof(double);
             budget = static_cast<size_t>(0.85 * static_cast<double>(fr + held));
         }
-        int64_t B = static_cast<int64_t>(budget / per_item);
-        if (B < 1) {
-            msg = "one " + std::to_string(k) + "-qubit item needs " + std::to_string(per_item) +
-                  " bytes, more than the memory budget of " + std::to_string(budget);
-            return QAOA_ENOMEM;
-        }
-        B = std::min<int64_t>(B, items);
-        // a pass launches up to tiles * B workgroups of <= 512 threads: keep the grid below 2^31
-        B = std::min<int64_t>(B, std::max<int64_t>(1, (int64_t{1} << 22) / tiles));
         // tiles (group 0: tile pairs) per workgroup: up to 8 while the class keeps >= 4096
         // workgroups (16 per CU); fixed per class, so an item's sums run in the same order
         // whatever the batching
         int tpw = 1;
         while (tpw < 8 && 2 * tpw <= tiles / 2 && items * tiles / (2 * tpw) >= 4096) tpw *= 2;
-        // no more items per batch than needed for 2^17 workgroups (512 per CU) per pass:
-        // larger batches hold more memory and gain little
-        if (!fixed_batches) B = std::min<int64_t>(B, std::max<int64_t>(1, ((int64_t{1} << 17) * tpw + tiles - 1) / tiles));
+        // items per batch: within the budget, the grid (a pass launches up to tiles * B
+        // workgroups of <= 512 threads: below 2^31 work-items) and no more than needed for
+        // 2^17 workgroups (512 per CU) per pass: larger batches hold more memory and gain little
+        auto batch_of = [&](size_t per_item) {
+            int64_t B = std::min<int64_t>(static_cast<int64_t>(budget / per_item), items);
+            B = std::min<int64_t>(B, std::max<int64_t>(1, (int64_t{1} << 22) / tiles));
+            return std::min<int64_t>(B, std::max<int64_t>(1, ((int64_t{1} << 17) * tpw + tiles - 1) / tiles));
+        };
+        bool ckpt = false;
+        if (grad && p >= 2) {
+            if (fixed_batches) ckpt = P->hbm_ckpt[gi] != 0;
+            else if (P->opt.checkpoint_mode == 1) ckpt = true;
+            // auto: store the forward states where the budget holds them without shrinking the batch
+            else if (P->opt.checkpoint_mode == 2) ckpt = budget >= per_ck && batch_of(per_ck) >= batch_of(per_unc);
+        }
+        const size_t per_item = ckpt ? per_ck : per_unc;
+        const int nphi = ckpt ? nck : 1;
+        int64_t B;
+        if (fixed_batches) {
+            B = P->hbm_batch[gi];
+        } else {
+            if (budget < per_item) {
+                msg = "one " + std::to_string(k) + "-qubit item needs " + std::to_string(per_item) +
+                      " bytes, more than the memory budget of " + std::to_string(budget);
+                return QAOA_ENOMEM;
+            }
+            B = batch_of(per_item);
+        }
         // free memory can be fragmented or held by other allocators: on a failed allocation
         // the batch is halved until one item does not fit either
         for (;;) {
             st = QAOA_OK;
-            if (need_phi) st = grow(P->d_phi, P->cap_phi, static_cast<size_t>(B) << kh, msg);
+            if (need_phi) st = grow(P->d_phi, P->cap_phi, (static_cast<size_t>(B) * nphi) << kh, msg);
             if (st == QAOA_OK && need_lam) st = grow(P->d_lam, P->cap_lam, static_cast<size_t>(B) << kh, msg);
             if (st == QAOA_OK) st = grow(P->d_gpart, P->cap_gpart, static_cast<size_t>(B) * tiles * stride, msg);
             if (st != QAOA_ENOMEM || B == 1) break;
@@ -393,7 +443,10 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         }
         if (st != QAOA_OK) return st;
         P->hbm_batch[gi] = B;
-        const std::vector<PassSpec> prog = hbm_program(k, p, grad);
+        P->hbm_ckpt[gi] = ckpt ? 1 : 0;
+        if (!fixed_batches && ckpt) P->checkpointed_classes += 1;
+        const std::vector<PassSpec> prog = hbm_program(k, p, grad, ckpt);
+        auto slot = [&](int j) { return P->d_phi + ((static_cast<size_t>(std::max(j, 0)) * B) << kh); };
         QCHECK(tm.begin(k, items));
         for (int64_t i0 = 0; i0 < items; i0 += B) {
             const int64_t nb = std::min<int64_t>(B, items - i0);
@@ -405,7 +458,9 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
                 pa.e_b = P->d_eb;
                 pa.e_w = P->d_ew;
                 pa.tt = P->d_tt;
-                pa.phi = P->d_phi;
+                pa.phi_in = slot(ps.ck_in);
+                pa.phi = ps.kind >= RV_GEN_MIX ? slot(ps.ck_in) : slot(ps.ck_out);
+                pa.store_phi = ps.store_phi;
                 pa.lam = P->d_lam;
                 pa.gpart = P->d_gpart;
                 pa.item0 = i0;

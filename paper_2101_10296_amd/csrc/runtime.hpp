@@ -61,7 +61,9 @@ struct qaoa_plan_s {
     float2* d_lam = nullptr;
     double* d_gpart = nullptr;
     std::vector<int64_t> hbm_batch;     // items per batch of each HBM group in the last call
+    std::vector<int8_t> hbm_ckpt;       // 1 if the HBM group stored forward checkpoints in the last call
     int64_t pass_launches[qaoa::N_PASS_KINDS] = {};   // per pass kind, last eager call
+    int32_t checkpointed_classes = 0;   // HBM groups that stored checkpoints in the last eager call
 
     // ---- graph replay (opts.graph)
     struct GraphKey {
@@ -113,11 +115,17 @@ hipError_t launch_tile_reduce(const ConeHbm* cones, const double* gpart, int64_t
 // One pass of the HBM program (see hbm_impl.hpp).
 struct PassSpec {
     int kind, group, la, lb, m0a, m0b;
-    int fix_layer = 0, fix_pow = 0;   // rescaling of psi in the first reverse pass
+    int fix_layer = 0, fix_pow = 0;   // rescaling of psi read as the forward sweep left it
+    int ck_in = -1, ck_out = -1;      // checkpoint slots read / written (-1: the single state buffer)
+    int store_phi = 1;                // reverse passes: write the undone psi back
 };
 int hbm_groups_of(int k);
 int hbm_group_qubits(int k, int grp);
-std::vector<PassSpec> hbm_program(int k, int p, bool grad);
+// ckpt: every forward pass but the final one writes its output to a slot of its own
+// (hbm_checkpoints(k, p) slots) and every reverse pass reads psi from the slot of the
+// forward pass it undoes instead of carrying the uncomputed psi along.
+std::vector<PassSpec> hbm_program(int k, int p, bool grad, bool ckpt = false);
+int hbm_checkpoints(int k, int p);
 
 hipError_t launch_scale_gamma_terms(double* g, int64_t P, int32_t p, int32_t M, double delta, hipStream_t st);
 // points per k_combine launch with ny blocks per point (grid below 2^32 work-items)

@@ -117,7 +117,7 @@ def test_error_codes(bad, status):
     assert len(str(ei.value)) > len("QAOA_EINVAL: ")
 
 
-@pytest.mark.parametrize("opts", [dict(checkpoint_mode=1), dict(k_lds_max=12), dict(k_lds_max=15),
+@pytest.mark.parametrize("opts", [dict(checkpoint_mode=3), dict(checkpoint_mode=-1), dict(k_lds_max=12), dict(k_lds_max=15),
                                   dict(max_cone_qubits=31), dict(mem_budget_bytes=-1),
                                   dict(graph=True, profile=True), dict(graph=True, one_cone_at_a_time=True)])
 def test_option_errors(opts):

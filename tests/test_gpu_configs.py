@@ -120,6 +120,20 @@ def test_config5ii_full_size(Q):
     _, zzo = oracle.energy(sub, ga[:1], be[:1])
     assert np.abs(zz[:1, ms] - zzo).max() <= ZZ_TOL
     pl.close()   # frees the state buffers (most of the device memory)
+    # the adjoint reading stored forward states (checkpoint_mode 1: up to five 4 GiB states
+    # per 30-qubit item): the same terms and gradient within the tolerances, and the stored
+    # oracle term gradients
+    plc = Q.Plan(g.n, g.edges, p=p, checkpoint_mode=1)
+    Ec, dgc, dbc, zzc, tgc = (x.cpu().numpy() for x in plc.energy_grad_terms(dev(ga), dev(be)))
+    assert plc.info()["checkpointed_classes"] > 0
+    plc.close()
+    assert np.abs(zzc - zzg).max() <= ZZ_TOL and np.abs(Ec - E).max() <= ZZ_TOL * g.m / 2
+    ginf = max(np.abs(dg).max(), np.abs(db).max())
+    assert max(np.abs(dgc - dg).max(), np.abs(dbc - db).max()) <= 1e-4 * max(ginf, 1e-3 * g.m)
+    for j, e in enumerate(gold["edges"]):
+        for i in range(gold["points"]):
+            ref = np.array(gold["dzz"][j][i])
+            assert np.abs(tgc[i, :, e] - ref).max() <= 1e-4 * max(np.abs(ref).max(), 1e-3), (e, i)
     # relabelled graph: same energies and gradients
     perm = np.random.default_rng(7).permutation(g.n)
     gr = W.relabel(g, perm)

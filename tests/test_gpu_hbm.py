@@ -130,14 +130,18 @@ STORED = {
 }
 
 
+@pytest.mark.parametrize("ckpt", [0, 1])
 @pytest.mark.parametrize("name", list(STORED))
-def test_stored_oracle_cases(Q, name):
+def test_stored_oracle_cases(Q, name, ckpt):
     # oracle values stored by tests/golden/make_oracle_golden.py; every term, the energy and
-    # the gradient at every stored point, and the pass kinds that produced them
+    # the gradient at every stored point, and the pass kinds that produced them; with the
+    # adjoint recovering the forward states by inverse layers (ckpt 0) and reading them
+    # from stored checkpoints (ckpt 1)
     c = _golden_cases()[name]
     g = getattr(W, c["family"])(*c["args"])
     ga, be = W.draw_angles(c["points"], c["p"], c["seed"])
-    pl = Q.Plan(g.n, g.edges, p=c["p"], generators=g.gens() if c["reduce"] else None, reduce=c["reduce"])
+    pl = Q.Plan(g.n, g.edges, p=c["p"], generators=g.gens() if c["reduce"] else None, reduce=c["reduce"],
+                checkpoint_mode=ckpt)
     eo, rep, _ = pl.orbits()
     assert list(rep) == c["rep"]
     kinds_fwd, kinds_grad = STORED[name]
@@ -147,6 +151,7 @@ def test_stored_oracle_cases(Q, name):
     E2, dg, db = pl.energy_grad(dev(ga), dev(be))
     ran = {i for i, n in enumerate(pl.info()["pass_launches"]) if n}
     assert ran == kinds_grad, ran
+    assert (pl.info()["checkpointed_classes"] > 0) == bool(ckpt)
     zz = zz.cpu().numpy()
     Wt = float(np.sum(c["W"]))
     assert np.abs(zz - np.array(c["zz"])).max() <= ZZ_TOL
@@ -160,13 +165,37 @@ def test_stored_oracle_cases(Q, name):
         assert err <= 1e-4 * max(ref_inf, 1e-3 * Wt), (i, err, ref_inf)
 
 
+@pytest.mark.parametrize("ckpt", [0, 1])
 @pytest.mark.parametrize("p", [4, 5])
-def test_deep_circuits_device_memory(Q, p):
+def test_deep_circuits_device_memory(Q, p, ckpt):
     # the 15- and 16-qubit stars at p = 4, 5: several boundary passes per group, both snake
-    # directions, and the first reverse pass's rescale at deeper layers
+    # directions, and the rescale of psi read as the forward sweep left it at deeper layers
+    # (the first reverse pass, or with stored checkpoints every reverse pass)
     ga, be = W.draw_angles(2, p, 80 + p)
     for m in (14, 15):
-        check_energy(Q, W.star(m), p, ga, be, grad=True)
+        pl, _, _ = check_energy(Q, W.star(m), p, ga, be, grad=True, plan_kw=dict(checkpoint_mode=ckpt))
+        assert (pl.info()["checkpointed_classes"] > 0) == bool(ckpt)
+
+
+def test_checkpoint_auto_and_budget(Q):
+    # auto stores the forward states where the budget holds them at the same batch size:
+    # it does under the default budget, not under a budget that fits the uncompute batch only
+    # (C_60(1,2,3) at p = 3: cones of 20-22 qubits, two stored states per item)
+    g = W.circulant(60, (1, 2, 3))
+    ga, be = W.draw_angles(2, 3, 13)
+    ref = Q.Plan(g.n, g.edges, p=3, generators=g.gens())
+    E0, dg0, db0 = ref.energy_grad(dev(ga), dev(be))
+    auto = Q.Plan(g.n, g.edges, p=3, generators=g.gens(), checkpoint_mode=2)
+    E1, dg1, db1 = auto.energy_grad(dev(ga), dev(be))
+    assert auto.info()["checkpointed_classes"] == auto.info()["n_hbm_cones"] > 0
+    tight = Q.Plan(g.n, g.edges, p=3, generators=g.gens(), checkpoint_mode=2,
+                   mem_budget_bytes=2 * (8 << 21) + (8 << 20))
+    E2, dg2, db2 = tight.energy_grad(dev(ga), dev(be))
+    assert tight.info()["checkpointed_classes"] < tight.info()["n_hbm_cones"]
+    for E, dg, db in ((E1, dg1, db1), (E2, dg2, db2)):
+        assert (E - E0).abs().max().item() <= ZZ_TOL * g.m / 2
+        scale = max(dg0.abs().max().item(), db0.abs().max().item())
+        assert max((dg - dg0).abs().max().item(), (db - db0).abs().max().item()) <= 1e-4 * scale
 
 
 def test_deep_weighted_star_rows_in_device_memory(Q):
