@@ -57,6 +57,27 @@ def fused_sources_sha256() -> str:
     return sources_sha256(("paper_2101_10296_amd/csrc/fused_impl.hpp", "paper_2101_10296_amd/csrc/fused_k14.hip"))
 
 
+def flops_model_8d(k: int, p: int) -> float:
+    """Algorithmic FP32 flops of one forward + adjoint cone evaluation by the hot-path
+    model: forward 2^k [p (6 + 3 k_int) + 6k (p - 1) + 12 + 3] (phase complex multiply and
+    cut count, full mixers of layers 1..p-1, the last two-qubit mixer, the expectation);
+    adjoint 3 x forward + 2^k p (8k + 8) (the inner products with sum_j X_j and C).
+    Counted on the stored half of the state (2^(k-1) amplitudes: cones of k >= 3 qubits are
+    invariant under flipping every qubit) with k_int = 0: cut values come from a table,
+    not a popcount.
+    """
+    n = float(1 << (k - 1 if k >= 3 else k))
+    fwd = p * 6 + 6 * k * (p - 1) + 12 + 3
+    return n * (3 * fwd + p * (8 * k + 8))
+
+
+def hbm_bytes_model_8d(k: int, p: int) -> float:
+    """Bytes of the one-sweep-per-layer model of the adjoint on a cone held in device
+    memory: 48 p bytes per stored amplitude (forward state stored once per layer, 16 p;
+    backward reads and writes psi and lambda once per layer, 32 p)."""
+    return 48.0 * p * float(1 << (k - 1))
+
+
 def flops_fwd_adj(k: int, p: int) -> float:
     """Algorithmic FP32 flops of one forward + adjoint cone evaluation (k qubits, depth p).
 
@@ -107,6 +128,54 @@ def cpu_model() -> str:
     except OSError:
         pass
     return platform.processor() or "unknown"
+
+
+_POOL_STATE = {}
+
+
+def _pool_init(graphs, ga, be):
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+    _POOL_STATE["plans"] = [oracle.plan(g.n, g.edges, None, gens, p, reduce=gens is not None)
+                            for g, p, gens in graphs]
+    _POOL_STATE["ga"], _POOL_STATE["be"] = ga, be
+
+
+def _pool_term(args):
+    import oracle
+    gi, m = args
+    pl = _POOL_STATE["plans"][gi]
+    sub = dict(pl, cones=[pl["cones"][m]], rep=pl["rep"][[m]], W=pl["W"][[m]])
+    oracle.energy_grad(sub, _POOL_STATE["ga"][:1], _POOL_STATE["be"][:1])
+    return gi
+
+
+def oracle_baseline_parallel(graphs, ga, be, budget_s: float, workers: int):
+    """The same sampled oracle work spread over `workers` processes (one term per task),
+    run for about budget_s seconds of wall time; per graph the extrapolated time is
+    wall * M / terms_done.  Call before the GPU is initialised (the pool forks)."""
+    import multiprocessing as mp
+    import oracle
+    Ms = [len(oracle.plan(g.n, g.edges, None, gens, p, reduce=gens is not None)["rep"]) for g, p, gens in graphs]
+    ctx = mp.get_context("fork")
+    total, desc = 0.0, []
+    with ctx.Pool(workers, initializer=_pool_init, initargs=(graphs, ga, be)) as pool:
+        pool.map(_pool_term, [(0, 0)] * workers)   # workers have built their plans
+        for gi, M in enumerate(Ms):
+            order = np.random.default_rng(0).permutation(M)
+            done, t0 = 0, time.perf_counter()
+            while done < M and time.perf_counter() - t0 < budget_s / len(graphs):
+                chunk = [(gi, int(m)) for m in order[done:done + 4 * workers]]
+                pool.map(_pool_term, chunk, chunksize=1)
+                done += len(chunk)
+            t = time.perf_counter() - t0
+            total += t * M / done
+            desc.append(f"{graphs[gi][0].name}: {done}/{M} terms at 1 point")
+    return 1.0 / total * len(graphs), "; ".join(desc)
 
 
 def oracle_baseline(graphs, ga, be, budget_s: float):
@@ -161,11 +230,12 @@ def hbm_measure(Q, torch, W, points: int) -> dict:
     pl.energy_grad(gt, bt)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    byts, ms, by_k = 0.0, 0.0, {}
+    byts, b8d, ms, by_k = 0.0, 0.0, 0.0, {}
     for k, items, t in pl.kernel_times():
         if k > 14:
             b = hbm_bytes_per_item(k, p, True) * items
             byts += b
+            b8d += hbm_bytes_model_8d(k, p) * items
             ms += t
             by_k[k] = round(b / (t * 1e-3) / 1e9, 1)
     pl.close()
@@ -180,7 +250,84 @@ def hbm_measure(Q, torch, W, points: int) -> dict:
             "kernel_ms": round(ms, 2), "algorithmic_GB": round(byts / 1e9, 2),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic},
-            "achieved_GBps_by_k": by_k}
+            "achieved_GBps_by_k": by_k,
+            "one_sweep_per_layer_model": {"GB": round(b8d / 1e9, 2),
+                                          "GBps": round(b8d / (ms * 1e-3) / 1e9, 1),
+                                          "frac": round(b8d / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}}
+
+
+def config4_measure(Q, torch, W) -> dict:
+    """The 48-graph mix (tori, hypercubes, circulants C_n(1,2,5), random 3- and 4-regular
+    graphs; p = 1 or 2; 32 angle points each), energy and gradient of every graph: one plan
+    per depth over all graphs of that depth (each reduced by its own generators), so one
+    call per depth evaluates every graph, with all cones of one size in one launch.  Plans
+    are built once and reused (a training step over the 48 graphs).  busy = summed HIP-event
+    kernel time over the wall time of the step; the device-memory classes of at least 18
+    qubits at p = 2 are reported with their algorithmic bytes over their kernel time."""
+    graphs, ga, be = W.workload("c4")
+    plans = []
+    t0 = time.perf_counter()
+    for p in (1, 2):
+        inst = [(g.n, g.edges, None, g.gens()) for g, pg in graphs if pg == p]
+        gt = torch.tensor(np.ascontiguousarray(ga[:, :p]), dtype=torch.float64, device="cuda")
+        bt = torch.tensor(np.ascontiguousarray(be[:, :p]), dtype=torch.float64, device="cuda")
+        plans.append((Q.Plan.batch(inst, p, profile=True), gt, bt, p, len(inst)))
+    plan_s = time.perf_counter() - t0
+    for pl, gt, bt, _, _ in plans:
+        pl.energy_grad(gt, bt)
+    torch.cuda.synchronize()
+    reps = 5
+    kern_ms, hbm_b, hbm_ms, hist, launches = 0.0, 0.0, 0.0, {}, 0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for pl, gt, bt, p, _ in plans:
+            pl.energy_grad(gt, bt)
+        torch.cuda.synchronize()
+        for pl, gt, bt, p, _ in plans:
+            for k, items, ms in pl.kernel_times():
+                kern_ms += ms
+                if k >= 18 and p >= 2:
+                    hbm_b += hbm_bytes_per_item(k, p, True) * items
+                    hbm_ms += ms
+                if k >= 2:
+                    hist[k] = hist.get(k, 0) + items // reps
+    wall = (time.perf_counter() - t0) / reps
+    n_orb = sum(pl.n_orbits for pl, *_ in plans)
+    for pl, *_ in plans:
+        pl.close()
+    evals = len(graphs) * ga.shape[0]
+    return {"workload": "48 graphs (3 tori, Q_8, Q_10, 13 circulants C_n(1,2,5), 15 random 3-regular, "
+                        "15 random 4-regular), p in {1, 2}, 32 points each, energy+gradient; one plan per "
+                        "depth over its graphs, plans reused",
+            "evals_per_s": round(evals / wall, 1), "ms_per_step": round(wall * 1e3, 3),
+            "calls_per_step": len(plans), "orbits": n_orb, "plan_s": round(plan_s, 3),
+            "gpu_busy_frac": round(kern_ms / reps / (wall * 1e3), 4),
+            "items_by_k": {str(k): v for k, v in sorted(hist.items())},
+            "hbm_k_ge_18_p2": {"GB": round(hbm_b / reps / 1e9, 3), "kernel_ms": round(hbm_ms / reps, 3),
+                               "achieved_GBps": round(hbm_b / (hbm_ms * 1e-3) / 1e9, 1) if hbm_ms else None}}
+
+
+def config5i_measure(Q, torch, W) -> dict:
+    """Hypercube Q_12 at p = 1: one orbit, one 24-qubit cone; energy and gradient at 8 points
+    (the p = 1 pass keeps no state: its roofline is the vector ALU)."""
+    (g, p), = W.workload("c5i")[0]
+    _, ga, be = W.workload("c5i")
+    gt = torch.tensor(ga, dtype=torch.float64, device="cuda")
+    bt = torch.tensor(be, dtype=torch.float64, device="cuda")
+    pl = Q.Plan(g.n, g.edges, p=p, generators=g.gens(), profile=True)
+    pl.energy_grad(gt, bt)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pl.energy_grad(gt, bt)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    ms = sum(t for k, _, t in pl.kernel_times() if k == 24)
+    pl.close()
+    return {"workload": "hypercube Q_12 (4096 nodes, 24576 edges, 1 orbit), p=1, 8 points, energy+gradient",
+            "evals_per_s": round(ga.shape[0] / wall, 2), "ms_per_call": round(wall * 1e3, 3),
+            "kernel_ms_k24": round(ms, 3), "symmetry_reduction": g.m}
 
 
 def replay_measure(Q, torch, W, calls: int = 200) -> dict:
@@ -325,7 +472,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--hbm-points", type=int, default=1,
+    ap.add_argument("--hbm-points", type=int, default=8,
                     help="angle points of the large-cone (device-memory) measurement; 0 = skip")
     ap.add_argument("--hbm-only", action="store_true", help="only the large-cone measurement")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -350,9 +497,15 @@ def main():
     (g2, _), = W.workload("c2ii")[0]
     _, ga, be = W.workload("c2i")
     P = ga.shape[0]
+    graphs = [(g1, p, g1.gens()), (g2, p, None)]
+    cpu_par = None
+    if not a.no_cpu_baseline:
+        # the oracle on all host cores first: the pool forks, so the GPU is not touched yet
+        workers = max(1, min(16, os.cpu_count() or 1))
+        v_par, sample_par = oracle_baseline_parallel(graphs, ga, be, a.cpu_budget, workers)
+        cpu_par = (v_par, sample_par, workers)
     gt = torch.tensor(ga, dtype=torch.float64, device="cuda")
     bt = torch.tensor(be, dtype=torch.float64, device="cuda")
-    graphs = [(g1, p, g1.gens()), (g2, p, None)]
 
     def step(profile=False):
         out = []
@@ -386,15 +539,19 @@ def main():
     # dominant kernel: the cone-size group with the largest total time
     (norb, kdom), (ms_dom, items_dom, pdom) = max(((k, v) for k, v in kernel_ms.items() if k[1] >= 2),
                                                   key=lambda kv: kv[1][0])
-    flop = flops_fwd_adj(kdom, pdom) * items_dom
+    flop = flops_model_8d(kdom, pdom) * items_dom
     achieved = flop / (ms_dom * 1e-3) / 1e12
+    executed = flops_fwd_adj(kdom, pdom) * items_dom / (ms_dom * 1e-3) / 1e12
     traffic = None   # counted HBM bytes per launch, if the counters are current for this kernel
     if kdom == 14 and fused_sources_sha256() == FUSED_TRAFFIC["sources_sha256"]:
         traffic = round(FUSED_TRAFFIC["bytes_per_item"] * items_dom / a.steps)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": f"k_fused<K={kdom},grad>", "avg_launch_ms": round(ms_dom / a.steps, 4),
-                "items_per_launch": items_dom // a.steps}
+                "items_per_launch": items_dom // a.steps,
+                "flop_per_item": flops_model_8d(kdom, pdom),
+                "executed_model": {"flop_per_item": flops_fwd_adj(kdom, pdom), "TFLOPs": round(executed, 3),
+                                   "frac": round(executed / PEAK_FP32_TFLOPS, 4)}}
 
     extra = {}
     if not a.no_plain:
@@ -418,7 +575,8 @@ def main():
         extra["speedup_vs_plain"] = round(t_plain / t_batched, 2)
         plain.close()
         batched.close()
-        # symmetry speedup on the circulant: unreduced all-edge plan over the reduced one
+        # symmetry speedup on the circulant: unreduced all-edge plan over the reduced one,
+        # each timed over 100 calls (energy and gradient at all 256 points, plans reused)
         red = Q.Plan(g1.n, g1.edges, p=p, generators=g1.gens())
         unr = Q.Plan(g1.n, g1.edges, p=p, reduce=False)
         for pl in (red, unr):
@@ -427,10 +585,13 @@ def main():
         ts = []
         for pl in (red, unr):
             t3 = time.perf_counter()
-            pl.energy_grad(gt, bt)
+            for _ in range(100):
+                pl.energy_grad(gt, bt)
             torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t3)
-        extra["symmetry_speedup_circulant"] = round(ts[1] / ts[0], 1)
+            ts.append((time.perf_counter() - t3) / 100)
+        extra["symmetry_speedup_circulant"] = {"reduced_ms": round(ts[0] * 1e3, 4),
+                                               "unreduced_ms": round(ts[1] * 1e3, 4),
+                                               "speedup": round(ts[1] / ts[0], 1), "calls": 100}
         red.close()
         unr.close()
         extra["graph_replay"] = replay_measure(Q, torch, W)
@@ -452,6 +613,9 @@ def main():
         "roofline": roofline,
     }
     line.update(extra)
+    if not a.no_plain:
+        line["config4"] = config4_measure(Q, torch, W)
+        line["config5i"] = config5i_measure(Q, torch, W)
     if a.hbm_points > 0:
         line["hbm"] = hbm_measure(Q, torch, W, a.hbm_points)
         # context for the HBM fraction: what a plain 4 GiB device-to-device copy reaches here
@@ -465,8 +629,12 @@ def main():
                 v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
         except ImportError:
             v, sample = oracle_baseline(graphs, ga, be, a.cpu_budget)
-        line["cpu_baseline"] = {"value": round(v, 6), "unit": "evals/s", "cores": 1, "kind": "oracle",
-                                "sample": sample + f" (FP64 numpy, {cpu_model()}, extrapolated to all terms)"}
+        v_par, sample_par, workers = cpu_par
+        line["cpu_baseline"] = {"value": round(v_par, 6), "unit": "evals/s", "cores": workers, "kind": "oracle",
+                                "sample": sample_par + f" per graph, one term per task over {workers} processes "
+                                          f"(FP64 numpy, {cpu_model()}, nproc {os.cpu_count()}, "
+                                          "extrapolated to all terms)",
+                                "one_core": {"value": round(v, 6), "cores": 1, "sample": sample}}
     print(json.dumps(line), flush=True)
 
 

@@ -131,6 +131,7 @@ typedef struct {
                                      7 undo of 0, 8 undo of 2, 9 undo of 3 */
     int32_t checkpointed_classes; /* device-memory cone-size classes whose adjoint read stored
                                      forward states in the last eagerly run call */
+    int32_t n_instances;          /* graphs planned together (qaoa_plan_batch), else 1 */
 } qaoa_plan_info;
 
 void qaoa_plan_opts_default(qaoa_plan_opts* opts);
@@ -147,6 +148,23 @@ void qaoa_plan_opts_default(qaoa_plan_opts* opts);
  * Errors: EINVAL, ENOTAUT, ECONE. */
 qaoa_status qaoa_plan_lightcones(const qaoa_problem* problem, const qaoa_plan_opts* opts,
                                  qaoa_plan_t* out);
+
+/* One plan over n_instances >= 1 graphs of the same depth p (problems[j].p equal), each
+ * validated, reduced by its own generators and cut into light cones exactly as by
+ * qaoa_plan_lightcones; the reduced sum of Sec. 3 is taken per instance.  Every cone of
+ * every instance then goes through the same launches: the cones of one size form one batch
+ * whatever instance they come from (Sec. 2.3: terms are independent).  Nodes, edges and
+ * orbits of instance j are numbered after those of instances 0..j-1 (qaoa_plan_orbits,
+ * qaoa_plan_cone, term_zz use these global ids; an instance's orbits are contiguous).
+ * Evaluation layouts for a plan with N instances (N = 1: as documented below):
+ *   gamma, beta [N][n_points][p] (instance j's points are its own),
+ *   energy [N][n_points], dgamma, dbeta [N][n_points][p],
+ *   term_zz [n_points][n_orbits], term_grad [n_points][2p][n_orbits] (orbit m of instance j
+ *   at instance j's point i).
+ * weight_unit in qaoa_plan_info is 0 when the instances' units differ.
+ * Errors: as qaoa_plan_lightcones, with the failing instance named in qaoa_last_error. */
+qaoa_status qaoa_plan_batch(const qaoa_problem* problems, int32_t n_instances,
+                            const qaoa_plan_opts* opts, qaoa_plan_t* out);
 
 /* Summary of a plan (host): sizes of the reduced problem of Sec. 3 (number of orbits M,
  * the cone-size histogram of Sec. 2.3) and device bookkeeping.  out is caller-owned.
@@ -197,26 +215,6 @@ qaoa_status qaoa_energy_grad_terms(qaoa_plan_t plan, int64_t n_points, const dou
                                    const double* beta, double* energy, double* dgamma,
                                    double* dbeta, double* term_zz, double* term_grad,
                                    qaoa_stream_t stream);
-
-/* For callers that cannot allocate device memory (code under HIP graph capture, tight
- * serving or training loops, harnesses that forbid hipMalloc): qaoa_energy_grad with every
- * per-call buffer (angle tables, per-term values) in a scratch array of
- * QAOA_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on until the process
- * ends.  It calls no hipMalloc or hipFree.  Same arguments and results as qaoa_energy_grad;
- * the points are processed in chunks that fit the array.
- *   - The plan must already be resident on the current device (its first qaoa_energy or
- *     qaoa_energy_grad call there uploads its tables) -> else QAOA_EINVAL.
- *   - Every cone must fit one workgroup (no cone above k_lds_max qubits: larger cones keep
- *     states of 2^(k-1) * 8 bytes in device memory) -> else QAOA_EINVAL.
- *   - One point must fit the array: p * (cut range + 1) * 8 + (2p + 1) * n_orbits * 8 bytes
- *     (plus alignment) <= QAOA_NOALLOC_SCRATCH_BYTES -> else QAOA_EINVAL.
- *   - All calls on one GPU share its array: calls that overlap on one GPU (other streams or
- *     threads) race; calls on one stream are ordered by it.
- * Errors: EINVAL, EHIP. */
-#define QAOA_NOALLOC_SCRATCH_BYTES (32u << 20)
-qaoa_status qaoa_energy_grad_noalloc(qaoa_plan_t plan, int64_t n_points, const double* gamma,
-                                     const double* beta, double* energy, double* dgamma,
-                                     double* dbeta, qaoa_stream_t stream);
 
 /* Diagnostics for plans built with opts.profile = 1: per kernel group of the last energy
  * call (one group per cone size k, plus the table and combine kernels, reported with

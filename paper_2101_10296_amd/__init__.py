@@ -41,29 +41,36 @@ def _i32(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
 
 
+def _problem(n_nodes, edges, p, weights, generators, keep):
+    """A qaoa_problem over host arrays that `keep` holds alive."""
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    u, v = _i32(e[:, 0]), _i32(e[:, 1])
+    w = None if weights is None else np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+    g = None if generators is None else _i32(generators).reshape(-1, int(n_nodes))
+    keep.extend([u, v, w, g])
+    pr = _capi.Problem()
+    pr.n_nodes = int(n_nodes)
+    pr.n_edges = int(e.shape[0])
+    pr.edge_u = u.ctypes.data_as(C.POINTER(C.c_int32))
+    pr.edge_v = v.ctypes.data_as(C.POINTER(C.c_int32))
+    pr.edge_w = None if w is None else w.ctypes.data_as(C.POINTER(C.c_double))
+    pr.n_generators = 0 if g is None else int(g.shape[0])
+    pr.generators = None if g is None or g.size == 0 else g.ctypes.data_as(C.POINTER(C.c_int32))
+    pr.p = int(p)
+    return pr
+
+
 class Plan:
-    """A planned problem: canonical edges, edge orbits and one light cone per orbit."""
+    """A planned problem: canonical edges, edge orbits and one light cone per orbit.
+
+    Plan.batch([...], p) plans several graphs together (one launch per cone size for all of
+    them); its evaluations take and return one block per instance (see energy())."""
 
     def __init__(self, n_nodes: int, edges, p: int, weights=None, generators=None, *, reduce: bool = True,
                  max_cone_qubits: int = 30, k_lds_max: int = 14, mem_budget_bytes: int = 0,
                  checkpoint_mode: int = 0, one_cone_at_a_time: bool = False, profile: bool = False,
-                 graph: bool = False):
+                 graph: bool = False, _instances=None):
         L = _capi.lib()
-        e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
-        self._u = _i32(e[:, 0])
-        self._v = _i32(e[:, 1])
-        self._w = None if weights is None else np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
-        g = None if generators is None else _i32(generators).reshape(-1, int(n_nodes))
-        self._g = g
-        pr = _capi.Problem()
-        pr.n_nodes = int(n_nodes)
-        pr.n_edges = int(e.shape[0])
-        pr.edge_u = self._u.ctypes.data_as(C.POINTER(C.c_int32))
-        pr.edge_v = self._v.ctypes.data_as(C.POINTER(C.c_int32))
-        pr.edge_w = None if self._w is None else self._w.ctypes.data_as(C.POINTER(C.c_double))
-        pr.n_generators = 0 if g is None else int(g.shape[0])
-        pr.generators = None if g is None or g.size == 0 else g.ctypes.data_as(C.POINTER(C.c_int32))
-        pr.p = int(p)
         o = _capi.PlanOpts()
         L.qaoa_plan_opts_default(C.byref(o))
         o.reduce = int(bool(reduce))
@@ -74,13 +81,30 @@ class Plan:
         o.one_cone_at_a_time = int(bool(one_cone_at_a_time))
         o.profile = int(bool(profile))
         o.graph = int(bool(graph))
+        keep = []
         h = C.c_void_p()
-        _check(L.qaoa_plan_lightcones(C.byref(pr), C.byref(o), C.byref(h)))
+        if _instances is None:
+            pr = _problem(n_nodes, edges, p, weights, generators, keep)
+            _check(L.qaoa_plan_lightcones(C.byref(pr), C.byref(o), C.byref(h)))
+        else:
+            arr = (_capi.Problem * len(_instances))()
+            for j, inst in enumerate(_instances):
+                arr[j] = _problem(inst[0], inst[1], p, inst[2] if len(inst) > 2 else None,
+                                  inst[3] if len(inst) > 3 else None, keep)
+            _check(L.qaoa_plan_batch(arr, len(_instances), C.byref(o), C.byref(h)))
         self._h = h
         self.p = int(p)
-        self.n_nodes = int(n_nodes)
-        self.n_edges = int(e.shape[0])
-        self.n_orbits = int(self.info()["n_orbits"])
+        inf = self.info()
+        self.n_nodes = int(inf["n_nodes"])
+        self.n_edges = int(inf["n_edges"])
+        self.n_orbits = int(inf["n_orbits"])
+        self.n_instances = int(inf["n_instances"])
+
+    @classmethod
+    def batch(cls, instances, p: int, **opts):
+        """One plan over several graphs of depth p: instances = [(n_nodes, edges[, weights[,
+        generators]]), ...].  Nodes, edges and orbits are numbered instance after instance."""
+        return cls(0, None, p, _instances=list(instances), **opts)
 
     # ---------------------------------------------------------------- host queries
     def info(self) -> dict:
@@ -126,16 +150,32 @@ class Plan:
 
     # ---------------------------------------------------------------- device evaluation
     def _angles(self, gamma, beta):
+        """(gamma, beta) as contiguous float64 [N * P, p] with N = n_instances: [P, p] inputs
+        are shared by every instance, [N, P, p] inputs give each instance its own points."""
         import torch
         if not (isinstance(gamma, torch.Tensor) and isinstance(beta, torch.Tensor)):
             raise TypeError("gamma and beta must be torch tensors on a HIP device")
         if gamma.device.type != "cuda" or beta.device.type != "cuda":
             raise ValueError("gamma and beta must live on the GPU")
-        g = gamma.detach().to(torch.float64).reshape(-1, self.p).contiguous()
-        b = beta.detach().to(torch.float64).reshape(-1, self.p).contiguous()
-        if g.shape != b.shape:
-            raise ValueError("gamma and beta must have the same shape [P, p]")
-        return g, b
+        if gamma.shape != beta.shape:
+            raise ValueError("gamma and beta must have the same shape")
+        N = self.n_instances
+        g = gamma.detach().to(torch.float64)
+        b = beta.detach().to(torch.float64)
+        if N > 1 and g.dim() == 3:
+            if g.shape[0] != N or g.shape[2] != self.p:
+                raise ValueError(f"per-instance angles must have shape [{N}, P, {self.p}]")
+        else:
+            g = g.reshape(-1, self.p)
+            b = b.reshape(-1, self.p)
+            if N > 1:
+                g = g.unsqueeze(0).expand(N, -1, -1)
+                b = b.unsqueeze(0).expand(N, -1, -1)
+        P = g.shape[-2]
+        return g.reshape(-1, self.p).contiguous(), b.reshape(-1, self.p).contiguous(), P
+
+    def _shape(self, P, *rest):
+        return (P, *rest) if self.n_instances == 1 else (self.n_instances, P, *rest)
 
     @staticmethod
     def _out(t, shape, device):
@@ -147,14 +187,14 @@ class Plan:
         return t
 
     def energy(self, gamma, beta, term_zz: bool = False, out=None):
-        """E [P] (and per-orbit <ZZ> [P, M] if term_zz) as cuda float64 tensors.
+        """E [P] (and per-orbit <ZZ> [P, M] if term_zz) as cuda float64 tensors; for a plan over
+        N > 1 instances E is [N, P] (gamma, beta [P, p] shared or [N, P, p] per instance).
 
         out: optional preallocated E (or (E, zz) with term_zz), e.g. to keep device pointers
         fixed for graph replay."""
-        g, b = self._angles(gamma, beta)
-        P = g.shape[0]
+        g, b, P = self._angles(gamma, beta)
         o = out if isinstance(out, (tuple, list)) else (out, None)
-        E = self._out(o[0], (P,), g.device)
+        E = self._out(o[0], self._shape(P), g.device)
         zz = self._out(o[1], (P, max(self.n_orbits, 1)), g.device) if term_zz else None
         import torch
         stream = torch.cuda.current_stream(g.device).cuda_stream
@@ -167,12 +207,11 @@ class Plan:
 
         out: optional preallocated (E, dgamma, dbeta)."""
         import torch
-        g, b = self._angles(gamma, beta)
-        P = g.shape[0]
+        g, b, P = self._angles(gamma, beta)
         o = out if out is not None else (None, None, None)
-        E = self._out(o[0], (P,), g.device)
-        dg = self._out(o[1], (P, self.p), g.device)
-        db = self._out(o[2], (P, self.p), g.device)
+        E = self._out(o[0], self._shape(P), g.device)
+        dg = self._out(o[1], self._shape(P, self.p), g.device)
+        db = self._out(o[2], self._shape(P, self.p), g.device)
         stream = torch.cuda.current_stream(g.device).cuda_stream
         _check(_capi.lib().qaoa_energy_grad(self._h, P, g.data_ptr(), b.data_ptr(), E.data_ptr(),
                                             dg.data_ptr(), db.data_ptr(), stream))
@@ -182,13 +221,12 @@ class Plan:
         """(E [P], dE/dgamma [P, p], dE/dbeta [P, p], zz [P, M], d zz / d(gamma, beta) [P, 2p, M]):
         the energy gradient together with every orbit term and its own gradient."""
         import torch
-        g, b = self._angles(gamma, beta)
-        P = g.shape[0]
+        g, b, P = self._angles(gamma, beta)
         dev = g.device
         M = max(self.n_orbits, 1)
-        E = torch.empty((P,), dtype=torch.float64, device=dev)
-        dg = torch.empty((P, self.p), dtype=torch.float64, device=dev)
-        db = torch.empty((P, self.p), dtype=torch.float64, device=dev)
+        E = torch.empty(self._shape(P), dtype=torch.float64, device=dev)
+        dg = torch.empty(self._shape(P, self.p), dtype=torch.float64, device=dev)
+        db = torch.empty(self._shape(P, self.p), dtype=torch.float64, device=dev)
         zz = torch.empty((P, M), dtype=torch.float64, device=dev)
         tg = torch.empty((P, 2 * self.p, M), dtype=torch.float64, device=dev)
         stream = torch.cuda.current_stream(dev).cuda_stream
@@ -250,8 +288,11 @@ def _autograd_fn():
         def backward(ctx, grad_out):
             dg, db = ctx.saved_tensors
             gs, bs, gdt, bdt = ctx.shapes
-            go = grad_out.to(torch.float64).reshape(-1, 1)
-            return (go * dg).reshape(gs).to(gdt), (go * db).reshape(bs).to(bdt), None
+            go = grad_out.to(torch.float64).unsqueeze(-1)
+            gg, gb = go * dg, go * db
+            if gg.dim() == 3 and len(gs) < 3:   # angles shared by every instance of a batch plan
+                gg, gb = gg.sum(0), gb.sum(0)
+            return gg.reshape(gs).to(gdt), gb.reshape(bs).to(bdt), None
 
     return QAOAEnergyFn
 

@@ -31,7 +31,8 @@ class PlanInfo(C.Structure):
                 ("total_weight", C.c_double), ("cut_min", C.c_int32), ("cut_max", C.c_int32),
                 ("n_hbm_cones", C.c_int64), ("device_bytes", C.c_int64),
                 ("graph_replays", C.c_int64), ("weight_unit", C.c_double),
-                ("pass_launches", C.c_int64 * 10), ("checkpointed_classes", C.c_int32)]
+                ("pass_launches", C.c_int64 * 10), ("checkpointed_classes", C.c_int32),
+                ("n_instances", C.c_int32)]
 
 
 _lib = None
@@ -49,6 +50,8 @@ def lib():
         L.qaoa_plan_opts_default.restype = None
         L.qaoa_plan_lightcones.argtypes = [C.POINTER(Problem), C.POINTER(PlanOpts), C.POINTER(vp)]
         L.qaoa_plan_lightcones.restype = i32
+        L.qaoa_plan_batch.argtypes = [C.POINTER(Problem), i32, C.POINTER(PlanOpts), C.POINTER(vp)]
+        L.qaoa_plan_batch.restype = i32
         L.qaoa_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
         L.qaoa_plan_query.restype = i32
         L.qaoa_plan_orbits.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)]

@@ -61,10 +61,8 @@ qaoa_status qaoa_find_generators(const qaoa_problem* pr, int32_t max_generators,
     }
 }
 
-qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* opts, qaoa_plan_t* out) {
-    if (!pr || !out) return set_err(QAOA_EINVAL, "problem or out is NULL");
-    *out = nullptr;
-    qaoa::PlanOptions o;
+namespace {
+qaoa_status plan_options(const qaoa_plan_opts* opts, qaoa::PlanOptions& o) {
     if (opts) {
         o.mem_budget_bytes = opts->mem_budget_bytes;
         o.reduce = opts->reduce;
@@ -82,11 +80,33 @@ qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* o
         if (o.checkpoint_mode < 0 || o.checkpoint_mode > 2)
             return set_err(QAOA_EINVAL, "checkpoint_mode must be 0 (uncompute), 1 (store) or 2 (auto)");
     }
+    return QAOA_OK;
+}
+
+qaoa_status make_plan(const qaoa_problem* pr, int32_t n_inst, const qaoa_plan_opts* opts, qaoa_plan_t* out) {
+    if (!pr || !out) return set_err(QAOA_EINVAL, "problems or out is NULL");
+    *out = nullptr;
+    if (n_inst < 1) return set_err(QAOA_EINVAL, "n_instances must be >= 1");
+    qaoa::PlanOptions o;
+    const qaoa_status so = plan_options(opts, o);
+    if (so != QAOA_OK) return so;
+    int32_t j = 0;
     try {
         auto* plan = new qaoa_plan_s();
         try {
-            qaoa::build_host_plan(pr->n_nodes, pr->n_edges, pr->edge_u, pr->edge_v, pr->edge_w, pr->n_generators,
-                                  pr->generators, pr->p, o, plan->hp);
+            if (n_inst == 1) {
+                qaoa::build_host_plan(pr->n_nodes, pr->n_edges, pr->edge_u, pr->edge_v, pr->edge_w, pr->n_generators,
+                                      pr->generators, pr->p, o, plan->hp);
+            } else {
+                std::vector<qaoa::HostPlan> parts(static_cast<size_t>(n_inst));
+                for (j = 0; j < n_inst; ++j) {
+                    const qaoa_problem& q = pr[j];
+                    qaoa::build_host_plan(q.n_nodes, q.n_edges, q.edge_u, q.edge_v, q.edge_w, q.n_generators,
+                                          q.generators, q.p, o, parts[j]);
+                }
+                j = -1;
+                qaoa::merge_host_plans(parts, plan->hp);
+            }
         } catch (...) {
             delete plan;
             throw;
@@ -96,10 +116,20 @@ qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* o
         g_last_error.clear();
         return QAOA_OK;
     } catch (const qaoa::PlanError& e) {
-        return set_err(e.status, e.msg);
+        return set_err(e.status, (n_inst > 1 && j >= 0 ? "instance " + std::to_string(j) + ": " : std::string()) + e.msg);
     } catch (const std::bad_alloc&) {
         return set_err(QAOA_ENOMEM, "host allocation failed while planning");
     }
+}
+}  // namespace
+
+qaoa_status qaoa_plan_lightcones(const qaoa_problem* pr, const qaoa_plan_opts* opts, qaoa_plan_t* out) {
+    return make_plan(pr, 1, opts, out);
+}
+
+qaoa_status qaoa_plan_batch(const qaoa_problem* problems, int32_t n_instances, const qaoa_plan_opts* opts,
+                            qaoa_plan_t* out) {
+    return make_plan(problems, n_instances, opts, out);
 }
 
 qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
@@ -125,6 +155,7 @@ qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
     out->weight_unit = plan->hp.delta;
     for (int i = 0; i < 10 && i < qaoa::N_PASS_KINDS; ++i) out->pass_launches[i] = plan->pass_launches[i];
     out->checkpointed_classes = plan->checkpointed_classes;
+    out->n_instances = hp.n_inst;
     return QAOA_OK;
 }
 

@@ -16,17 +16,17 @@ struct ConeDev {
     int32_t cut_shift;  // cone.cut_min - plan.cut_min: offset into a phase table row
     int32_t cut_min;    // smallest possible cut value of the cone
     int32_t cut_range;  // cut_max - cut_min + 1
-    int32_t pad_;
+    int32_t inst;       // instance of the cone (plans over several graphs; angle tables per instance)
 };
 
 // Arguments of one energy evaluation that every kernel needs.
 struct EvalArgs {
-    int32_t P;              // angle points
+    int32_t P;              // angle points (per instance)
     int32_t p;              // depth
-    int32_t M;              // terms (orbits)
+    int32_t M;              // terms (orbits, all instances)
     int32_t R;              // phase-table row length (global cut range + 1)
-    const float2* phase;    // [P][p][R]: exp(-i gamma_l c), c = plan.cut_min + index
-    const float2* mix;      // [P][p]: (tau_l, |kappa_l|^2) of the factored mixer exp(-i beta_l X)
+    const float2* phase;    // [inst][P][p][R]: exp(-i gamma_l delta_inst c), c = plan.cut_min + index
+    const float2* mix;      // [inst][P][p]: (tau_l, |kappa_l|^2) of the factored mixer exp(-i beta_l X)
     double* zz;             // [P][M]
     double* g;              // [P][2p][M]: d zz / d gamma_l (l < p), d zz / d beta_l (p <= l < 2p)
 };

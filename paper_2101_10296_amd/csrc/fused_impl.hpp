@@ -554,8 +554,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     const uint8_t* cut = cutl + il * C::N;
     float2* xb = xbuf + (C::S > 1 ? il * C::NPAD : 0);
     float2* xb2 = DB ? xbuf + (C::S > 1 ? (C::IPW + il) * C::NPAD : 0) : nullptr;
-    const float2* phase0 = ea.phase + static_cast<size_t>(point) * p * ea.R + cd.cut_shift;
-    const float2* mix0 = ea.mix + static_cast<size_t>(point) * p;
+    const size_t ipt = static_cast<size_t>(cd.inst) * P + point;   // angle point of the cone's instance
+    const float2* phase0 = ea.phase + ipt * p * ea.R + cd.cut_shift;
+    const float2* mix0 = ea.mix + ipt * p;
     // phase rows of every layer for this item: prow[il][l][c] = exp(-i gamma_l (cut_min + c)),
     // staged in LDS; GR: they do not fit beside the kernel's LDS (deep circuits with many
     // items per workgroup) and are read from the table in device memory instead

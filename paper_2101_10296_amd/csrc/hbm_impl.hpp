@@ -68,6 +68,8 @@ struct ConeHbm {
     int32_t cut_shift;   // cut_min - plan.cut_min: offset into a phase table row
     int64_t tt_off[4];   // byte offset of the C_tt table of each group
     int32_t tt_min[4];   // value subtracted before storing C_tt as a byte
+    int32_t inst;        // instance of the cone (angle tables per instance)
+    int32_t pad_;
 };
 
 struct PassArgs {
@@ -391,7 +393,8 @@ k_pass(PassArgs pa) {
     const int32_t k0_base = pa.cones[cslot].tt_min[pa.group] - cd.cut_min;
     if (CUTS && tid < 32) tpos[tid] = -1;
     // the phase rows a pass reads -> LDS: [0] layer 1, [1] layer lb, [2] layer p
-    const float2* ph0 = pa.ea.phase + static_cast<size_t>(point) * p * pa.ea.R + cd.cut_shift;
+    const size_t ipt = static_cast<size_t>(cd.inst) * P + point;   // angle point of the cone's instance
+    const float2* ph0 = pa.ea.phase + ipt * p * pa.ea.R + cd.cut_shift;
     const float2* row_first = rows;
     const float2* row_lb = rows + pa.rowcap;
     const float2* row_last = rows + 2 * pa.rowcap;
@@ -467,7 +470,7 @@ k_pass(PassArgs pa) {
     };
     float2* xb = xbuf;
     float2* xb2 = DB ? xbuf + H::NPAD : nullptr;
-    const float2* mix0 = pa.ea.mix + static_cast<size_t>(point) * p;
+    const float2* mix0 = pa.ea.mix + ipt * p;
     auto kpowK = [&](float k2) { return exp2f(0.5f * k * log2f(k2)); };
     const float k2p = mix0[p - 1].y;
     constexpr int RL = HS::rot(HS::S - 1);   // last processing layout

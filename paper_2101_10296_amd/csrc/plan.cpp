@@ -335,6 +335,62 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
         P.cut_min = std::min<int32_t>(P.cut_min, c.cut_min);
         P.cut_max = std::max<int32_t>(P.cut_max, c.cut_max);
     }
+    P.n_inst = 1;
+    P.inst_node = {0, n};
+    P.inst_edge = {0, m};
+    P.inst_orbit = {0, M};
+    P.inst_delta = {P.delta};
+}
+
+void merge_host_plans(std::vector<HostPlan>& parts, HostPlan& P) {
+    if (parts.empty()) fail(kEINVAL, "no instances");
+    P = HostPlan{};
+    P.p = parts[0].p;
+    P.n_inst = static_cast<int32_t>(parts.size());
+    P.inst_node.assign(1, 0);
+    P.inst_edge.assign(1, 0);
+    P.inst_orbit.assign(1, 0);
+    P.unit = true;
+    P.delta = parts[0].delta;
+    int64_t n_total = 0;
+    for (const HostPlan& h : parts) n_total += h.n;
+    if (n_total > INT32_MAX) fail(kEINVAL, "the instances hold more than 2^31 - 1 nodes in all");
+    for (int32_t j = 0; j < P.n_inst; ++j) {
+        HostPlan& h = parts[j];
+        if (h.p != P.p) fail(kEINVAL, "instance " + std::to_string(j) + ": every instance needs the same p");
+        const int32_t n0 = P.n;
+        const int64_t e0 = P.m, o0 = static_cast<int64_t>(P.rep.size());
+        P.n += h.n;
+        P.m += h.m;
+        for (int64_t e = 0; e < h.m; ++e) {
+            P.u.push_back(h.u[e] + n0);
+            P.v.push_back(h.v[e] + n0);
+            P.edge_orbit.push_back(static_cast<int32_t>(h.edge_orbit[e] + o0));
+        }
+        P.w.insert(P.w.end(), h.w.begin(), h.w.end());
+        P.wi.insert(P.wi.end(), h.wi.begin(), h.wi.end());
+        for (size_t o = 0; o < h.rep.size(); ++o) {
+            P.rep.push_back(h.rep[o] + e0);
+            P.size.push_back(h.size[o]);
+            P.W.push_back(h.W[o]);
+        }
+        for (Cone& c : h.cones) {
+            for (int32_t& x : c.nodes) x += n0;
+            c.inst = j;
+            P.cones.push_back(std::move(c));
+        }
+        P.total_weight += h.total_weight;
+        P.cut_min = std::min(P.cut_min, h.cut_min);
+        P.cut_max = std::max(P.cut_max, h.cut_max);
+        P.unit = P.unit && h.unit;
+        if (h.delta != P.delta) P.delta = 0.0;   // no single unit: see inst_delta
+        P.inst_node.push_back(P.n);
+        P.inst_edge.push_back(P.m);
+        P.inst_orbit.push_back(static_cast<int64_t>(P.rep.size()));
+        P.inst_delta.push_back(h.delta);
+        h = HostPlan{};
+    }
+    if (static_cast<int64_t>(P.rep.size()) > INT32_MAX) fail(kEINVAL, "more than 2^31 - 1 orbits in all");
 }
 
 }  // namespace qaoa

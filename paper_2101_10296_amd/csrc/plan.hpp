@@ -20,6 +20,7 @@ struct Cone {
     std::vector<int32_t> ea, eb;           // induced edges as qubit pairs, ea < eb
     std::vector<int32_t> ew;               // integer weight of each induced edge
     int32_t cut_min = 0, cut_max = 0;      // range of the cut value C(x) over all x
+    int32_t inst = 0;                      // instance (graph) of a plan over several graphs
 };
 
 struct HostPlan {
@@ -36,6 +37,13 @@ struct HostPlan {
     std::vector<Cone> cones;               // [M]
     double total_weight = 0.0;
     int32_t cut_min = 0, cut_max = 0;      // over all cones
+    // instances: a plan over several graphs is their disjoint union with each graph's nodes,
+    // edges and orbits numbered contiguously; weights of instance j count in its own unit
+    int32_t n_inst = 1;
+    std::vector<int32_t> inst_node;        // [n_inst + 1] first node of each instance
+    std::vector<int64_t> inst_edge;        // [n_inst + 1] first edge
+    std::vector<int64_t> inst_orbit;       // [n_inst + 1] first orbit
+    std::vector<double> inst_delta;        // [n_inst] weight unit of each instance
 };
 
 struct PlanOptions {
@@ -53,6 +61,10 @@ struct PlanOptions {
 void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev, const double* ew,
                      int32_t n_gen, const int32_t* gens, int32_t p, const PlanOptions& opt,
                      HostPlan& out);
+
+// One plan over several graphs of the same depth: the planned instances, concatenated
+// (node, edge and orbit ids offset by the sizes of the instances before them).
+void merge_host_plans(std::vector<HostPlan>& parts, HostPlan& out);
 
 // Automorphism generators of a weighted graph by individualisation and refinement
 // (autgen.cpp).  Returns 0, or -1 with msg on bad input.

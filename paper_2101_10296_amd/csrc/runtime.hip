@@ -190,7 +190,7 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         d.cut_shift = c.cut_min - hp.cut_min;
         d.cut_min = c.cut_min;
         d.cut_range = c.cut_max - c.cut_min + 1;
-        d.pad_ = 0;
+        d.inst = c.inst;
         cut_bytes += std::max<int64_t>(int64_t{1} << c.k, 16);
         ea.insert(ea.end(), c.ea.begin(), c.ea.end());
         eb.insert(eb.end(), c.eb.begin(), c.eb.end());
@@ -215,6 +215,7 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         d.cut_min = c.cut_min;
         d.cut_range = c.cut_max - c.cut_min + 1;
         d.cut_shift = c.cut_min - hp.cut_min;
+        d.inst = c.inst;
         d.n_groups = hbm_groups_of(c.k - 1);
         max_groups = std::max(max_groups, d.n_groups);
         for (int g = 0; g < d.n_groups; ++g) {
@@ -250,6 +251,17 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
     QCHECK(hipMalloc(&P->d_ew, ne * sizeof(int32_t)));
     QCHECK(hipMalloc(&P->d_hcones, std::max<size_t>(hc.size(), 1) * sizeof(ConeHbm)));
     QCHECK(hipMalloc(&P->d_tt, std::max<int64_t>(tt_bytes, 16)));
+    QCHECK(hipMalloc(&P->d_inst_orbit, hp.inst_orbit.size() * sizeof(int64_t)));
+    QCHECK(hipMalloc(&P->d_inst_delta, hp.inst_delta.size() * sizeof(double)));
+    QCHECK(hipMemcpy(P->d_inst_orbit, hp.inst_orbit.data(), hp.inst_orbit.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice));
+    QCHECK(hipMemcpy(P->d_inst_delta, hp.inst_delta.data(), hp.inst_delta.size() * sizeof(double),
+                     hipMemcpyHostToDevice));
+    {
+        const std::vector<double> ones(hp.inst_delta.size(), 1.0);
+        QCHECK(hipMalloc(&P->d_ones, ones.size() * sizeof(double)));
+        QCHECK(hipMemcpy(P->d_ones, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     if (M) QCHECK(hipMemcpy(P->d_cones, cd.data(), cd.size() * sizeof(ConeDev), hipMemcpyHostToDevice));
     if (Mall) QCHECK(hipMemcpy(P->d_W, hp.W.data(), hp.W.size() * sizeof(double), hipMemcpyHostToDevice));
     if (!hc.empty()) QCHECK(hipMemcpy(P->d_hcones, hc.data(), hc.size() * sizeof(ConeHbm), hipMemcpyHostToDevice));
@@ -263,7 +275,8 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
                             P->d_tt, nullptr));
     QCHECK(hipDeviceSynchronize());
     P->resident_bytes = cd.size() * sizeof(ConeDev) + static_cast<size_t>(cut_bytes) + hp.W.size() * sizeof(double) +
-                        hc.size() * sizeof(ConeHbm) + static_cast<size_t>(tt_bytes) + 3 * ne * sizeof(int32_t);
+                        hc.size() * sizeof(ConeHbm) + static_cast<size_t>(tt_bytes) + 3 * ne * sizeof(int32_t) +
+                        hp.inst_orbit.size() * sizeof(int64_t) + 2 * hp.inst_delta.size() * sizeof(double);
     P->device = dev;
     P->dev_ready = true;
     return QAOA_OK;
@@ -331,7 +344,7 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
     const int32_t p = hp.p;
     const int32_t M = static_cast<int32_t>(hp.cones.size());
     const int32_t R = hp.cut_max - hp.cut_min + 1;
-    const size_t npl = static_cast<size_t>(n_points) * p;
+    const size_t npl = static_cast<size_t>(hp.n_inst) * n_points * p;   // (instance, point, layer) rows
     if ((st = grow(P->d_phase, P->cap_phase, npl * R, msg)) != QAOA_OK) return st;
     if ((st = grow(P->d_mix, P->cap_mix, npl, msg)) != QAOA_OK) return st;
     double* zz = term_zz;
@@ -348,8 +361,8 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
     }
     GroupTimer tm(P, stream);
     QCHECK(tm.begin(-1, static_cast<int64_t>(npl)));
-    QCHECK(launch_tables(gamma, beta, static_cast<int64_t>(npl), R, hp.cut_min, hp.delta, P->d_phase, P->d_mix,
-                         stream));
+    QCHECK(launch_tables(gamma, beta, static_cast<int64_t>(npl), R, hp.cut_min, P->d_inst_delta,
+                         static_cast<int64_t>(n_points) * p, P->d_phase, P->d_mix, stream));
     QCHECK(tm.end());
     EvalArgs ea{static_cast<int32_t>(n_points), p, M, R, P->d_phase, P->d_mix, zz, g};
     for (const auto& grp : P->lds_groups) {
@@ -485,13 +498,20 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         QCHECK(tm.end());
     }
     QCHECK(tm.begin(-2, n_points));
-    double delta = hp.delta;
-    if (grad && term_grad && delta != 1.0) {
-        // the caller reads the per-term gradient: gamma derivatives in radians
-        QCHECK(launch_scale_gamma_terms(g, n_points, p, M, delta, stream));
-        delta = 1.0;
+    if (grad && term_grad) {
+        // the caller reads the per-term gradient: gamma derivatives in radians (the combination
+        // then scales by the unit once more, so it gets unit weights)
+        bool unit = true;
+        for (double d : hp.inst_delta) unit = unit && d == 1.0;
+        if (!unit) {
+            QCHECK(launch_scale_gamma_terms(g, n_points, p, M, P->d_inst_orbit, hp.n_inst, P->d_inst_delta, stream));
+        }
+        QCHECK(launch_combine(P->d_W, zz, g, M, p, P->d_inst_orbit, unit ? P->d_inst_delta : P->d_ones, hp.n_inst,
+                              n_points, n_points, 0, energy, dgamma, dbeta, stream));
+    } else {
+        QCHECK(launch_combine(P->d_W, zz, g, M, p, P->d_inst_orbit, P->d_inst_delta, hp.n_inst, n_points, n_points,
+                              0, energy, dgamma, dbeta, stream));
     }
-    QCHECK(launch_combine(P->d_W, zz, g, M, p, n_points, delta, energy, dgamma, dbeta, stream));
     QCHECK(tm.end());
     return QAOA_OK;
 }
@@ -574,6 +594,12 @@ void release_device(qaoa_plan_s* P) {
     hipFree(P->d_phi);
     hipFree(P->d_lam);
     hipFree(P->d_gpart);
+    hipFree(P->d_inst_orbit);
+    hipFree(P->d_inst_delta);
+    hipFree(P->d_ones);
+    P->d_inst_orbit = nullptr;
+    P->d_inst_delta = nullptr;
+    P->d_ones = nullptr;
     P->d_hcones = nullptr;
     P->d_ea = P->d_eb = P->d_ew = nullptr;
     P->d_tt = nullptr;

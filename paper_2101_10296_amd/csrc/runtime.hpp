@@ -39,6 +39,9 @@ struct qaoa_plan_s {
     int32_t *d_ea = nullptr, *d_eb = nullptr, *d_ew = nullptr;
     uint8_t* d_tt = nullptr;
     double* d_W = nullptr;
+    int64_t* d_inst_orbit = nullptr;    // [n_inst + 1]
+    double* d_inst_delta = nullptr;     // [n_inst]
+    double* d_ones = nullptr;           // [n_inst] of 1.0 (combination of per-term gradients in radians)
     size_t resident_bytes = 0;
 
     // ---- profiling (opts.profile): events around each kernel group of the last call
@@ -102,7 +105,7 @@ qaoa_status kernel_times(qaoa_plan_s* plan, int32_t cap, int32_t* k_out, int64_t
 hipError_t launch_fused(int K, bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
                         const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st);
 hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, int32_t R, int32_t cmin,
-                         double delta, float2* phase, float2* mix, hipStream_t st);
+                         const double* deltas, int64_t pl_per_inst, float2* phase, float2* mix, hipStream_t st);
 hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
                              const int32_t* ew, uint8_t* tables, hipStream_t st);
 hipError_t launch_pass(int kind, const PassArgs& pa, hipStream_t st);
@@ -127,10 +130,14 @@ int hbm_group_qubits(int k, int grp);
 std::vector<PassSpec> hbm_program(int k, int p, bool grad, bool ckpt = false);
 int hbm_checkpoints(int k, int p);
 
-hipError_t launch_scale_gamma_terms(double* g, int64_t P, int32_t p, int32_t M, double delta, hipStream_t st);
+hipError_t launch_scale_gamma_terms(double* g, int64_t P, int32_t p, int32_t M, const int64_t* inst_orbit,
+                                    int32_t n_inst, const double* deltas, hipStream_t st);
 // points per k_combine launch with ny blocks per point (grid below 2^32 work-items)
 int64_t combine_chunk(uint32_t ny);
-hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p, int64_t P,
-                          double delta, double* energy, double* dgamma, double* dbeta, hipStream_t st);
+// energy [n_inst][P_out], dgamma / dbeta [n_inst][P_out][p]: points i0 .. i0 + Pc - 1 of
+// each instance from the term rows zz [Pc][M], g [Pc][2p][M]
+hipError_t launch_combine(const double* W, const double* zz, const double* g, int32_t M, int32_t p,
+                          const int64_t* inst_orbit, const double* deltas, int32_t n_inst, int64_t Pc,
+                          int64_t P_out, int64_t i0, double* energy, double* dgamma, double* dbeta, hipStream_t st);
 
 }  // namespace qaoa

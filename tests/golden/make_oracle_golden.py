@@ -46,9 +46,9 @@ NO_TERMS = {"c3_rand3_n1000_p2_all"}
 # Term cases: forward <Z_u Z_v> of selected edges of an unreduced plan, at the first
 # `points` angle points of a workload.  name -> (workload name, edge indices, points)
 # random 3-regular n = 200, p = 3: the first two edges whose cones have 24, 25 and 26
-# qubits (three pass groups of stored qubits) and the first 28-qubit one.
+# qubits (three pass groups of stored qubits) and edge 0, whose cone has 29 qubits.
 TERM_CASES = {
-    "c5ii_terms_k24_28": ("c5ii", [4, 21, 23, 65, 15, 16, 0], 1),
+    "c5ii_terms_k24_29": ("c5ii", [4, 21, 23, 65, 15, 16, 0], 1),
 }
 # Term-gradient cases: <Z_u Z_v> and its derivatives in (gamma_1..p, beta_1..p) of selected
 # edges of an unreduced plan.  name -> (workload name, edge indices, points)

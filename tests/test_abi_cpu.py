@@ -174,3 +174,42 @@ def test_first_failing_cone_is_reported():
     cones = oracle.plan(g.n, g.edges, None, None, 1, reduce=True, max_k=40)["cones"]
     bad = [m for m, c in enumerate(cones) if x in c["nodes"] and y in c["nodes"]]
     assert f"cone of orbit {min(bad)} " in str(ei.value)
+
+
+def test_batch_plan_concatenates_instances():
+    # a plan over three graphs: each instance's orbits, representatives and cones are those
+    # of its own plan, numbered after the instances before it
+    graphs = [(W.circulant(40, (1, 2)), True, None), (W.random_regular(30, 3, 4), False, None),
+              (W.torus2d(5), True, np.full(50, 0.5))]
+    inst = [(g.n, g.edges, w, g.gens() if red else None) for g, red, w in graphs]
+    bp = Q.Plan.batch(inst, 2)
+    info = bp.info()
+    assert info["n_instances"] == 3 and bp.n_instances == 3
+    assert info["weight_unit"] == 0.0   # units 1 and 1/2
+    eo, rep, size = bp.orbits()
+    n0 = e0 = o0 = 0
+    for (g, red, w) in graphs:
+        single = Q.Plan(g.n, g.edges, p=2, weights=w, generators=g.gens() if red else None)
+        seo, srep, ssize = single.orbits()
+        M = len(srep)
+        np.testing.assert_array_equal(eo[e0:e0 + g.m], seo + o0)
+        np.testing.assert_array_equal(rep[o0:o0 + M], srep + e0)
+        np.testing.assert_array_equal(size[o0:o0 + M], ssize)
+        for m in range(M):
+            k, nodes, ne = bp.cone(o0 + m)
+            ks, snodes, sne = single.cone(m)
+            assert (k, ne) == (ks, sne) and np.array_equal(nodes, snodes + n0)
+        n0, e0, o0 = n0 + g.n, e0 + g.m, o0 + M
+    assert (info["n_nodes"], info["n_edges"], info["n_orbits"]) == (n0, e0, o0)
+
+
+def test_batch_plan_errors_name_the_instance():
+    g = W.circulant(12, (1,))
+    bad = np.arange(g.n)[::-1].copy()
+    bad[0], bad[1] = bad[1], bad[0]
+    with pytest.raises(Q.QaoaError) as ei:
+        Q.Plan.batch([(g.n, g.edges), (g.n, g.edges, None, bad[None, :])], 1)
+    assert ei.value.status == Q.QAOA_ENOTAUT and "instance 1" in str(ei.value)
+    with pytest.raises(Q.QaoaError) as ei:
+        Q.Plan.batch([], 1)
+    assert ei.value.status == Q.QAOA_EINVAL

@@ -6,7 +6,7 @@
   the energy / gradient consistency of every plan;
 * random 3-regular n=200 at p=3 (300 cones of 20-30 qubits) at its first two angle points
   (bench.py times them): every cone of up to 22 qubits term by term against the oracle,
-  stored oracle terms of sampled 24-, 25-, 26- and 28-qubit cones (three pass groups) and
+  stored oracle terms of sampled 24-, 25-, 26- and 29-qubit cones (three pass groups) and
   stored oracle term gradients of a 24- and a 25-qubit cone; for all of it, the invariance
   of energy and gradient under a relabelling of the nodes (which changes every cone's qubit
   order, so every kernel data path differs).
@@ -52,6 +52,7 @@ def test_config4_mixed_graphs(Q):
     full_oracle = {"torus32x32", "Q8"}
     rng = np.random.default_rng(4)
     n_full = 0
+    single = {}
     for gi, (g, p) in enumerate(graphs):
         gam, bet = ga[:, :p], be[:, :p]
         pl = Q.Plan(g.n, g.edges, p=p, generators=g.gens())
@@ -59,6 +60,7 @@ def test_config4_mixed_graphs(Q):
         E2, dg, db = pl.energy_grad(dev(gam), dev(bet))
         E, zz, E2 = E.cpu().numpy(), zz.cpu().numpy(), E2.cpu().numpy()
         dg, db = dg.cpu().numpy(), db.cpu().numpy()
+        single[gi] = (E2, dg, db)
         ref = oracle.plan(g.n, g.edges, None, g.gens(), p, reduce=True, max_k=30)
         Wt = float(np.sum(ref["W"]))
         assert np.array_equal(pl.orbits()[1], ref["rep"])
@@ -82,6 +84,17 @@ def test_config4_mixed_graphs(Q):
             _grad_close(dg[:2], db[:2], dgo, dbo, Wt)
             n_full += 1
     assert n_full >= 5
+    # the same 48 graphs as two batch plans (one per depth, one call each): every graph's
+    # block equals its own plan's result up to the rounding of the orbit-weighted sums
+    for p in (1, 2):
+        ids = [gi for gi, (g, pg) in enumerate(graphs) if pg == p]
+        bp = Q.Plan.batch([(graphs[gi][0].n, graphs[gi][0].edges, None, graphs[gi][0].gens()) for gi in ids], p)
+        Eb, dgb, dbb = (x.cpu().numpy() for x in bp.energy_grad(dev(ga[:, :p]), dev(be[:, :p])))
+        for j, gi in enumerate(ids):
+            Es, dgs, dbs = single[gi]
+            m = graphs[gi][0].m
+            assert np.abs(Eb[j] - Es).max() <= 1e-12 * m
+            assert max(np.abs(dgb[j] - dgs).max(), np.abs(dbb[j] - dbs).max()) <= 1e-12 * m
 
 
 def test_config5ii_full_size(Q):
@@ -99,7 +112,7 @@ def test_config5ii_full_size(Q):
     assert np.isfinite(zz).all() and np.abs(zz).max() <= 1 + 1e-5
     assert np.abs(zzg - zz).max() <= ZZ_TOL
     # stored oracle values (tests/golden/make_oracle_golden.py) of cones too large to rerun
-    gold = _golden("term_cases")["c5ii_terms_k24_28"]
+    gold = _golden("term_cases")["c5ii_terms_k24_29"]
     for j, e in enumerate(gold["edges"]):
         assert pl.cone(e)[0] == gold["k"][j]
         assert np.abs(zz[:gold["points"], e] - np.array(gold["zz"])[:, j]).max() <= ZZ_TOL, e
