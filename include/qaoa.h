@@ -216,6 +216,26 @@ qaoa_status qaoa_energy_grad_terms(qaoa_plan_t plan, int64_t n_points, const dou
                                    double* dbeta, double* term_zz, double* term_grad,
                                    qaoa_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid hipMalloc): qaoa_energy_grad with every
+ * per-call buffer (angle tables, per-term values) in a scratch array of
+ * QAOA_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on until the process
+ * ends.  It calls no hipMalloc or hipFree.  Same arguments and results as qaoa_energy_grad;
+ * the points are processed in chunks that fit the array.
+ *   - The plan must already be resident on the current device (its first qaoa_energy or
+ *     qaoa_energy_grad call there uploads its tables) -> else QAOA_EINVAL.
+ *   - Every cone must fit one workgroup (no cone above k_lds_max qubits: larger cones keep
+ *     states of 2^(k-1) * 8 bytes in device memory) -> else QAOA_EINVAL.
+ *   - One point must fit the array: p * (cut range + 1) * 8 + (2p + 1) * n_orbits * 8 bytes
+ *     (plus alignment) <= QAOA_NOALLOC_SCRATCH_BYTES -> else QAOA_EINVAL.
+ *   - All calls on one GPU share its array: calls that overlap on one GPU (other streams or
+ *     threads) race; calls on one stream are ordered by it.
+ * Errors: EINVAL, EHIP. */
+#define QAOA_NOALLOC_SCRATCH_BYTES (32u << 20)
+qaoa_status qaoa_energy_grad_noalloc(qaoa_plan_t plan, int64_t n_points, const double* gamma,
+                                     const double* beta, double* energy, double* dgamma,
+                                     double* dbeta, qaoa_stream_t stream);
+
 /* Diagnostics for plans built with opts.profile = 1: per kernel group of the last energy
  * call (one group per cone size k, plus the table and combine kernels, reported with
  * k = -1 and k = -2), the cone size, the number of (cone, point) items and the elapsed
