@@ -102,21 +102,22 @@ def hbm_groups(kh: int) -> int:
     return 1 + (kh - 13 + 8) // 9
 
 
-def hbm_bytes_per_item(k: int, p: int, grad: bool) -> float:
+def hbm_bytes_per_item(k: int, p: int, grad: bool, ckpt: bool = False) -> float:
     """Algorithmic HBM bytes of one (cone, point) item of the device-memory pass program.
 
     8 B per stored complex64 amplitude read or written; the stored half of the state has
     2^(k-1) amplitudes (qubit k-1 = 0).  Forward: the first pass writes the state, every
     later pass reads and writes it, the final pass only reads it (with the gradient it also
-    writes lambda).  Reverse: every pass but the last reads and writes psi and lambda; the
-    last (undoing the first forward pass) only reads them.  p = 1 keeps no state.
+    writes lambda).  Reverse: every pass but the last reads and writes psi and lambda (with
+    stored checkpoints, ckpt, it reads both and writes lambda only); the last (undoing the
+    first forward pass) only reads them.  p = 1 keeps no state.
     """
     if p == 1:
         return 0.0
     F = (p - 1) * (hbm_groups(k - 1) - 1)   # passes after the first (at least two groups)
     n = float(1 << (k - 1))
     if grad:
-        return n * (8 + 16 * (F - 1) + 16 + 16 + 32 * (F - 1))
+        return n * (8 + 16 * (F - 1) + 16 + 16 + (24 if ckpt else 32) * (F - 1))
     return n * (8 + 16 * (F - 1) + 8)
 
 
@@ -208,7 +209,7 @@ def oracle_baseline(graphs, ga, be, budget_s: float):
     return 1.0 / total * len(graphs), "; ".join(desc)
 
 
-def hbm_measure(Q, torch, W, points: int) -> dict:
+def hbm_measure(Q, torch, W, points: int, ckpt: int = 0) -> dict:
     """Large cones: random 3-regular n=200 at p=3 (300 cones of 20-30 qubits), energy and
     gradient at the first `points` angle points, through the device-memory pass kernels.
     The plan is built and evaluated once (device tables, state buffers), then timed on a
@@ -222,7 +223,7 @@ def hbm_measure(Q, torch, W, points: int) -> dict:
     gt = torch.tensor(ga[:points], dtype=torch.float64, device="cuda")
     bt = torch.tensor(be[:points], dtype=torch.float64, device="cuda")
     t0 = time.perf_counter()
-    pl = Q.Plan(g.n, g.edges, p=p, profile=True)
+    pl = Q.Plan(g.n, g.edges, p=p, profile=True, checkpoint_mode=ckpt)
     pl.energy_grad(gt, bt)          # first call: device tables and state buffers
     torch.cuda.synchronize()
     first = time.perf_counter() - t0
@@ -230,10 +231,12 @@ def hbm_measure(Q, torch, W, points: int) -> dict:
     pl.energy_grad(gt, bt)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    info = pl.info()
+    stored = info["checkpointed_classes"] > 0
     byts, b8d, ms, by_k = 0.0, 0.0, 0.0, {}
     for k, items, t in pl.kernel_times():
         if k > 14:
-            b = hbm_bytes_per_item(k, p, True) * items
+            b = hbm_bytes_per_item(k, p, True, bool((info["checkpointed_k_mask"] >> k) & 1)) * items
             byts += b
             b8d += hbm_bytes_model_8d(k, p) * items
             ms += t
@@ -241,10 +244,13 @@ def hbm_measure(Q, torch, W, points: int) -> dict:
     pl.close()
     gbs = byts / (ms * 1e-3) / 1e9
     traffic = None   # counted HBM bytes of the timed evaluation, if the counters are current
-    if hbm_sources_sha256() == HBM_TRAFFIC["sources_sha256"]:
+    if hbm_sources_sha256() == HBM_TRAFFIC["sources_sha256"] and not stored:
         traffic = round(byts * HBM_TRAFFIC["counted_over_algorithmic"])
     return {"workload": f"random 3-regular n=200 (seed 502), p=3, {points} point(s), energy+gradient, "
                         "300 cones of 20-30 qubits in device memory",
+            "adjoint": ("forward states read from stored checkpoints (checkpoint_mode %d, %d of %d cone-size "
+                        "classes)" % (ckpt, info["checkpointed_classes"], len(by_k))) if stored
+                       else "forward states recovered by inverse layers (checkpoint_mode 0)",
             "evals_per_s": round(points / wall, 4), "wall_s": round(wall, 3),
             "first_call_s_incl_plan_and_alloc": round(first, 3),
             "kernel_ms": round(ms, 2), "algorithmic_GB": round(byts / 1e9, 2),
@@ -475,6 +481,7 @@ def main():
     ap.add_argument("--hbm-points", type=int, default=8,
                     help="angle points of the large-cone (device-memory) measurement; 0 = skip")
     ap.add_argument("--hbm-only", action="store_true", help="only the large-cone measurement")
+    ap.add_argument("--checkpoint-mode", type=int, default=0, help="adjoint mode of --hbm-only (0, 1, 2)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="also time a device-to-device copy of this many GiB (counter calibration)")
     a = ap.parse_args()
@@ -487,7 +494,7 @@ def main():
     import workloads as W
 
     if a.hbm_only:
-        out = {"hbm": hbm_measure(Q, torch, W, max(a.hbm_points, 1))}
+        out = {"hbm": hbm_measure(Q, torch, W, max(a.hbm_points, 1), ckpt=a.checkpoint_mode)}
         if a.copy_gib > 0:
             out["copy"] = copy_measure(torch, a.copy_gib)
         print(json.dumps(out), flush=True)
@@ -618,6 +625,9 @@ def main():
         line["config5i"] = config5i_measure(Q, torch, W)
     if a.hbm_points > 0:
         line["hbm"] = hbm_measure(Q, torch, W, a.hbm_points)
+        # the same workload with the adjoint reading stored forward states where the budget
+        # allows (checkpoint_mode 2): time and bytes beside the uncompute program
+        line["hbm_checkpointed"] = hbm_measure(Q, torch, W, a.hbm_points, ckpt=2)
         # context for the HBM fraction: what a plain 4 GiB device-to-device copy reaches here
         line["hbm"]["device_copy_GBps"] = copy_measure(torch, 4.0)["GBps_read_plus_write"]
     if a.copy_gib > 0:

@@ -97,7 +97,9 @@ typedef struct {
                                          c = passes per forward sweep - 1; less traffic, no
                                          FP32 drift of the uncomputation);
                                      2 = auto: store where the memory budget holds the extra
-                                         states without fewer items per batch, else uncompute */
+                                         states without fewer items per batch, or with a batch
+                                         that still gives every pass 2^15 workgroups; else
+                                         uncompute */
     int32_t one_cone_at_a_time;   /* 1 = plain GPU path: one launch per (cone, point) */
     int32_t profile;              /* 1 = record HIP events around every kernel group of each
                                      energy call (read with qaoa_plan_kernel_times) */
@@ -132,6 +134,7 @@ typedef struct {
     int32_t checkpointed_classes; /* device-memory cone-size classes whose adjoint read stored
                                      forward states in the last eagerly run call */
     int32_t n_instances;          /* graphs planned together (qaoa_plan_batch), else 1 */
+    uint32_t checkpointed_k_mask; /* bit k set: the k-qubit class read stored forward states */
 } qaoa_plan_info;
 
 void qaoa_plan_opts_default(qaoa_plan_opts* opts);

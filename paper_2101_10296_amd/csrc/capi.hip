@@ -155,6 +155,7 @@ qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
     out->weight_unit = plan->hp.delta;
     for (int i = 0; i < 10 && i < qaoa::N_PASS_KINDS; ++i) out->pass_launches[i] = plan->pass_launches[i];
     out->checkpointed_classes = plan->checkpointed_classes;
+    out->checkpointed_k_mask = plan->checkpointed_k_mask;
     out->n_instances = hp.n_inst;
     return QAOA_OK;
 }

@@ -167,30 +167,33 @@ __device__ __forceinline__ void hxpose_dual(float2 (&f)[A], float2 (&l)[A], floa
 }
 
 // Mixer on the processed tile bits of layout ROT (tile bit b is processed when bit b of
-// pm is set; a butterfly with tau = 0 is the identity).  Wrapped bits belong to rotation 0.
-template <int CF, int ROT, int LB = -1, int A>
+// pm is set).  Wrapped bits belong to rotation 0.  ALL: every tile bit is processed (group
+// 0); otherwise the bits of pm that are clear (a last group with fewer than nine qubits) are
+// skipped by a uniform branch.
+template <int CF, int ROT, int LB = -1, bool ALL = false, int A>
 __device__ __forceinline__ void hmix(float2 (&v)[A], float t, uint32_t pm) {
     constexpr int AB = Hz<CF>::AB;
     if constexpr (LB >= 0) {
         // tile bit LB sits on lane bit 0 of this layout: partner in the neighbouring lane
-        const float ti = ((pm >> LB) & 1u) ? t : 0.f;
+        if (ALL || ((pm >> LB) & 1u)) {
 #pragma unroll
-        for (int r = 0; r < A; ++r) {
-            const float2 q = lane_x1(v[r]);
-            v[r] = make_float2(fmaf(ti, q.y, v[r].x), fmaf(-ti, q.x, v[r].y));
-            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            for (int r = 0; r < A; ++r) {
+                const float2 q = lane_x1(v[r]);
+                v[r] = make_float2(fmaf(t, q.y, v[r].x), fmaf(-t, q.x, v[r].y));
+                if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
         if (ROT + i >= HT) continue;
-        const float ti = ((pm >> (ROT + i)) & 1u) ? t : 0.f;
+        if (!ALL && !((pm >> (ROT + i)) & 1u)) continue;
         int nb = 0;
 #pragma unroll
         for (int r = 0; r < A; ++r)
             if (!(r & (1 << i))) {
-                bfly(v[r], v[r | (1 << i)], ti);
+                bfly(v[r], v[r | (1 << i)], t);
                 if ((++nb & 7) == 0) __builtin_amdgcn_sched_barrier(0);
             }
         __builtin_amdgcn_sched_barrier(0);
@@ -198,15 +201,15 @@ __device__ __forceinline__ void hmix(float2 (&v)[A], float t, uint32_t pm) {
 }
 
 // Undo the mixer on the processed bits of layout ROT for psi and lambda; returns the
-// weighted share of Im <lambda| sum_j X_j |psi> (see unmix_stage2).
-template <int CF, int ROT, int LB = -1, int A>
+// weighted share of Im <lambda| sum_j X_j |psi> (see unmix_stage2).  ALL as in hmix.
+template <int CF, int ROT, int LB = -1, bool ALL = false, int A>
 __device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w, uint32_t pm) {
     constexpr int AB = Hz<CF>::AB;
     float acc = 0.f;
     if constexpr (LB >= 0) {
+      if (ALL || ((pm >> LB) & 1u)) {
         // lane bit 0: term on the values before the undo, with the weight before this bit
-        const bool act = (pm >> LB) & 1u;
-        const float ti = act ? -t : 0.f;
+        const float ti = -t;
         float a = 0.f;
 #pragma unroll
         for (int r = 0; r < A; ++r) {
@@ -217,15 +220,16 @@ __device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t
             l[r] = make_float2(fmaf(ti, lq.y, l[r].x), fmaf(-ti, lq.x, l[r].y));
             if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        acc = act ? w * a : 0.f;
-        w = act ? w * k2 : w;
+        acc = w * a;
+        w = w * k2;
         __builtin_amdgcn_sched_barrier(0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < AB; ++i) {
         if (ROT + i >= HT) continue;
-        const bool act = (pm >> (ROT + i)) & 1u;
-        const float ti = act ? -t : 0.f;
+        if (!ALL && !((pm >> (ROT + i)) & 1u)) continue;
+        const float ti = -t;
         float a0 = 0.f, a1 = 0.f;
         int np = 0;
 #pragma unroll
@@ -238,9 +242,8 @@ __device__ __forceinline__ float hunmix2(float2 (&f)[A], float2 (&l)[A], float t
                 else xacc(a0, l[r], l[r2], f[r], f[r2]);
                 if ((np & 3) == 0) __builtin_amdgcn_sched_barrier(0);
             }
-        const float wn = act ? w * k2 : w;
-        acc = fmaf(act ? wn : 0.f, a0 + a1, acc);
-        w = wn;
+        w *= k2;
+        acc = fmaf(w, a0 + a1, acc);
         __builtin_amdgcn_sched_barrier(0);
     }
     return acc;
@@ -270,7 +273,7 @@ __device__ __forceinline__ void hmix_group(float2 (&f)[A], float2* xb, uint32_t 
         constexpr int st = DESC ? H::S - 1 - j : j;
         constexpr int prev = (j == 0) ? FROM_ROT : H::rot(DESC ? H::S - j : j - 1);
         if constexpr (prev != H::rot(st)) hxpose<CF, prev, H::rot(st)>(f, xb, tau);
-        hmix<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1)>(f, t, pm);
+        hmix<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1), G0>(f, t, pm);
     });
 }
 
@@ -291,9 +294,78 @@ __device__ __forceinline__ float hunmix_group(float2 (&f)[A], float2 (&l)[A], fl
                 hxpose<CF, prev, H::rot(st)>(l, xb, tau);
             }
         }
-        acc += hunmix2<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1)>(f, l, t, k2, w, pm);
+        acc += hunmix2<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1), G0>(f, l, t, k2, w, pm);
     });
     return acc;
+}
+
+// Im <lambda| X_j |psi> for the processed bits j of layout ROT with both states held at one
+// point of the layer (no butterfly: X_j commutes with every mixer of the layer, so the
+// inner products may be taken anywhere inside it).  ALL as in hmix.
+template <int CF, int ROT, int LB = -1, bool ALL = false, int A>
+__device__ __forceinline__ float hip_stage(const float2 (&f)[A], const float2 (&l)[A], uint32_t pm) {
+    constexpr int AB = Hz<CF>::AB;
+    float a0 = 0.f, a1 = 0.f;
+    if constexpr (LB >= 0) {
+        if (ALL || ((pm >> LB) & 1u)) {
+#pragma unroll
+            for (int r = 0; r < A; ++r) {
+                cacc((r & 1) ? a1 : a0, 1.f, l[r], lane_x1(f[r]));
+                if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < AB; ++i) {
+        if (ROT + i >= HT) continue;
+        if (!ALL && !((pm >> (ROT + i)) & 1u)) continue;
+        int np = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                const int r2 = r | (1 << i);
+                if (np++ & 1) xacc(a1, l[r], l[r2], f[r], f[r2]);
+                else xacc(a0, l[r], l[r2], f[r], f[r2]);
+                if ((np & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return a0 + a1;
+}
+
+// The inner products of every processed bit of the group, walking layouts 0 .. S-1 with
+// psi and lambda transposed together (one LDS buffer each when DB).  Ends in layout S-1.
+template <int CF, bool G0, bool DB = false, int A>
+__device__ __forceinline__ float hip_group(float2 (&f)[A], float2 (&l)[A], float2* xb, uint32_t tau, uint32_t pm,
+                                           float2* xb2 = nullptr) {
+    using H = HStages<CF, G0>;
+    float acc = 0.f;
+    static_for<0, H::S>([&](auto J) {
+        constexpr int st = decltype(J)::value;
+        if constexpr (st > 0) {
+            if constexpr (DB) {
+                hxpose_dual<CF, H::rot(st - 1), H::rot(st)>(f, l, xb, xb2, tau);
+            } else {
+                hxpose<CF, H::rot(st - 1), H::rot(st)>(f, xb, tau);
+                hxpose<CF, H::rot(st - 1), H::rot(st)>(l, xb, tau);
+            }
+        }
+        acc += hip_stage<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1), G0>(f, l, pm);
+    });
+    return acc;
+}
+
+// Undo of the group's mixer on one state (the inverse butterflies only), walking layouts
+// S-1 .. 0 from layout S-1.  Ends in layout 0.
+template <int CF, bool G0, int A>
+__device__ __forceinline__ void hunmix_group1(float2 (&v)[A], float2* xb, uint32_t tau, float t, uint32_t pm) {
+    using H = HStages<CF, G0>;
+    static_for<0, H::S>([&](auto J) {
+        constexpr int st = H::S - 1 - decltype(J)::value;
+        if constexpr (st < H::S - 1) hxpose<CF, H::rot(st + 1), H::rot(st)>(v, xb, tau);
+        hmix<CF, H::rot(st), (st == H::S - 1 ? H::LB : -1), G0>(v, -t, pm);
+    });
 }
 
 // Mixer of the dropped qubit k-1 between the two tiles of a pair (partner in the same
@@ -673,20 +745,32 @@ k_pass(PassArgs pa) {
                     for (int t = 0; t < NT; ++t)
                         a += cgrad_stage<true>(f[t], lm[t], pk[t], row_last, cd.cut_min, mu);
                     part[2] += 2.0 * static_cast<double>(mu) * mu * a;
-                    // undo mixer la = p-1 on this group (state sits in rotation 0)
+                    // mixer la = p-1 on this group: psi is not needed after this pass (the next
+                    // reverse pass reads it from device memory), so the inner products of all
+                    // the group's qubits are taken at this point of the layer (both states
+                    // at the scale |kappa|^-m0a: weight |kappa|^2m0a), and only lambda is
+                    // then undone
                     const float2 tka = mix0[pa.la - 1];
                     const float w0 = exp2f(pa.m0a * log2f(tka.y));
-                    float w = w0, b = 0.f;
+                    float b = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        w = w0;
-                        b += hunmix_group<CF, G0, false, 0, DB>(f[t], lm[t], xb, tau, tka.x, tka.y, w, pm, xb2);
+                    for (int t = 0; t < NT; ++t) b += hip_group<CF, G0, DB>(f[t], lm[t], xb, tau, pm, xb2);
+                    if constexpr (PAIR) {
+                        float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+                        for (int r = 0; r < A; ++r) {
+                            if (r & 1) xacc(a1, lm[0][r], lm[1][r], f[0][r], f[1][r]);
+                            else xacc(a0, lm[0][r], lm[1][r], f[0][r], f[1][r]);
+                            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                        }
+                        b += a0 + a1;
+                        hflip(lm[0], lm[1], -tka.x);
                     }
-                    if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tka.x, tka.y, w);
-                    part[3] += 2.0 * static_cast<double>(b);
+                    part[3] += 2.0 * static_cast<double>(w0) * static_cast<double>(b);
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
-                        hxpose<CF, RL, RIO>(lm[t], xb, tau);
+                        hunmix_group1<CF, G0>(lm[t], xb, tau, tka.x, pm);
+                        hxpose<CF, 0, RIO>(lm[t], xb, tau);
                         store(lm[t], pa.lam, off[t], t);
                     }
                 }

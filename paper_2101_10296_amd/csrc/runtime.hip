@@ -383,6 +383,7 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         P->hbm_ckpt.assign(P->hbm_groups.size(), 0);
         std::fill(std::begin(P->pass_launches), std::end(P->pass_launches), int64_t{0});
         P->checkpointed_classes = 0;
+        P->checkpointed_k_mask = 0;
     }
     for (size_t gi = 0; gi < P->hbm_groups.size(); ++gi) {
         const auto& grp = P->hbm_groups[gi];
@@ -423,8 +424,11 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         if (grad && p >= 2) {
             if (fixed_batches) ckpt = P->hbm_ckpt[gi] != 0;
             else if (P->opt.checkpoint_mode == 1) ckpt = true;
-            // auto: store the forward states where the budget holds them without shrinking the batch
-            else if (P->opt.checkpoint_mode == 2) ckpt = budget >= per_ck && batch_of(per_ck) >= batch_of(per_unc);
+            // auto: store the forward states where the budget holds them without shrinking the
+            // batch, or with a batch that still gives every pass 2^15 workgroups (128 per CU)
+            else if (P->opt.checkpoint_mode == 2)
+                ckpt = budget >= per_ck && (batch_of(per_ck) >= batch_of(per_unc) ||
+                                            batch_of(per_ck) * tiles / (2 * tpw) >= (int64_t{1} << 15));
         }
         const size_t per_item = ckpt ? per_ck : per_unc;
         const int nphi = ckpt ? nck : 1;
@@ -457,7 +461,10 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         if (st != QAOA_OK) return st;
         P->hbm_batch[gi] = B;
         P->hbm_ckpt[gi] = ckpt ? 1 : 0;
-        if (!fixed_batches && ckpt) P->checkpointed_classes += 1;
+        if (!fixed_batches && ckpt) {
+            P->checkpointed_classes += 1;
+            P->checkpointed_k_mask |= 1u << k;
+        }
         const std::vector<PassSpec> prog = hbm_program(k, p, grad, ckpt);
         auto slot = [&](int j) { return P->d_phi + ((static_cast<size_t>(std::max(j, 0)) * B) << kh); };
         QCHECK(tm.begin(k, items));

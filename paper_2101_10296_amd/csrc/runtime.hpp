@@ -67,6 +67,7 @@ struct qaoa_plan_s {
     std::vector<int8_t> hbm_ckpt;       // 1 if the HBM group stored forward checkpoints in the last call
     int64_t pass_launches[qaoa::N_PASS_KINDS] = {};   // per pass kind, last eager call
     int32_t checkpointed_classes = 0;   // HBM groups that stored checkpoints in the last eager call
+    uint32_t checkpointed_k_mask = 0;   // bit k: the k-qubit class did
 
     // ---- graph replay (opts.graph)
     struct GraphKey {
