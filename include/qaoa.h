@@ -43,10 +43,10 @@ typedef int32_t qaoa_status;
 enum {
     QAOA_OK = 0,
     QAOA_EINVAL = -1,   /* bad sizes or ids, self-loop, duplicate edge, p outside [1, 1024],
-                           n_points outside [1, 2^30],
-                           weights without a common unit (the GPU path counts cut values in it) */
+                           n_points outside [1, 2^30], non-finite weights */
     QAOA_ENOTAUT = -2,  /* a generator is not a weight-preserving automorphism */
-    QAOA_ECONE = -3,    /* a light cone exceeds max_cone_qubits, or its cut range exceeds 255 */
+    QAOA_ECONE = -3,    /* a light cone exceeds max_cone_qubits, or a cone held in device
+                           memory (above 14 qubits) has real weights (see edge_w) */
     QAOA_ENOMEM = -4,   /* not even one work item fits the memory budget / device memory */
     QAOA_EHIP = -5      /* HIP runtime error (no device, launch failure, ...) */
 };
@@ -64,11 +64,14 @@ typedef struct {
     int64_t n_edges;              /* |E| >= 0; the input order is the edge index */
     const int32_t* edge_u;        /* [n_edges], 0 <= id < n_nodes */
     const int32_t* edge_v;        /* [n_edges] */
-    const double* edge_w;         /* [n_edges] weights, or NULL = unit weights.  They must be
-                                     integer multiples of one common unit (integers, or
-                                     rationals with denominators up to 2^20 to 1e-13 relative),
-                                     at most 2^24 units
-                                     each; a cone's cut values may span at most 255 units */
+    const double* edge_w;         /* [n_edges] finite weights, or NULL = unit weights.  Weights
+                                     that are integer multiples of one common unit (integers,
+                                     or rationals with denominators up to 2^20 to 1e-13
+                                     relative, at most 2^24 units each) with cut values
+                                     spanning at most 255 units per cone use integer cut
+                                     tables; any other weights (irrational, Gaussian
+                                     couplings, wide ranges) use real cut values per amplitude,
+                                     for cones of at most 14 qubits (else QAOA_ECONE) */
     int32_t n_generators;         /* >= 0 */
     const int32_t* generators;    /* row-major [n_generators][n_nodes]: image of node i under
                                      generator g; NULL / 0 = trivial group */
@@ -135,6 +138,10 @@ typedef struct {
                                      forward states in the last eagerly run call */
     int32_t n_instances;          /* graphs planned together (qaoa_plan_batch), else 1 */
     uint32_t checkpointed_k_mask; /* bit k set: the k-qubit class read stored forward states */
+    int32_t real_weights;         /* 1: the weights have no common unit (or a cone's cut values
+                                     span more than 255 units): the phase of every amplitude
+                                     is computed from its own real cut value (FP64 reduction of
+                                     the angle, FP32 sine and cosine); weight_unit is 0 */
 } qaoa_plan_info;
 
 void qaoa_plan_opts_default(qaoa_plan_opts* opts);

@@ -32,7 +32,8 @@ class PlanInfo(C.Structure):
                 ("n_hbm_cones", C.c_int64), ("device_bytes", C.c_int64),
                 ("graph_replays", C.c_int64), ("weight_unit", C.c_double),
                 ("pass_launches", C.c_int64 * 10), ("checkpointed_classes", C.c_int32),
-                ("n_instances", C.c_int32), ("checkpointed_k_mask", C.c_uint32)]
+                ("n_instances", C.c_int32), ("checkpointed_k_mask", C.c_uint32),
+                ("real_weights", C.c_int32)]
 
 
 _lib = None

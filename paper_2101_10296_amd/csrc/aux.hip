@@ -58,6 +58,37 @@ __global__ void k_cut_tables(const ConeDev* __restrict__ cones, const int32_t* _
     }
 }
 
+// Real-weight cut table of cone c over the stored half (qubit k-1 = 0 for k >= 3):
+// table[x] = C(x) - c0 as a float, C(x) = sum over cone edges of w_ab [x_a != x_b] summed
+// in FP64 (MaxCut cost with real couplings, Sec. 2.4 and Sec. 4).
+__global__ void k_cut_tables_real(const ConeDev* __restrict__ cones, const int32_t* __restrict__ ea,
+                                  const int32_t* __restrict__ eb, const double* __restrict__ ew,
+                                  float* __restrict__ tables) {
+    const ConeDev cd = cones[blockIdx.x];
+    const uint32_t N = 1u << (cd.k >= 3 ? cd.k - 1 : cd.k);
+    float* out = tables + cd.cut_off;
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) {
+        double c = 0.0;
+        for (int32_t e = 0; e < cd.n_edges; ++e) {
+            const int32_t a = ea[cd.edge_off + e], b = eb[cd.edge_off + e];
+            if (((x >> a) ^ (x >> b)) & 1u) c += ew[cd.edge_off + e];
+        }
+        out[x] = static_cast<float>(c - static_cast<double>(cd.c0));
+    }
+}
+
+hipError_t launch_cut_tables_real(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
+                                  const double* ew, float* tables, hipStream_t st) {
+    constexpr int64_t CH = static_cast<int64_t>(UINT32_MAX) / 256;
+    for (int64_t c0 = 0; c0 < n_cones; c0 += CH) {
+        const unsigned nx = static_cast<unsigned>(n_cones - c0 < CH ? n_cones - c0 : CH);
+        hipLaunchKernelGGL(k_cut_tables_real, dim3(nx), dim3(256), 0, st, cones + c0, ea, eb, ew, tables);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Per (instance j, point i) block, over the orbits m of instance j:
 // block y == 0: energy = sum_m W_m (1 - zz[i][m]) / 2            (Sec. 3 reduced sum)
 // block y == 1 + l: -1/2 sum_m W_m g[i][l][m] -> dgamma (l < p, times the instance's weight

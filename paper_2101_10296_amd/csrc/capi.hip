@@ -152,7 +152,8 @@ qaoa_status qaoa_plan_query(qaoa_plan_t plan, qaoa_plan_info* out) {
     out->cut_max = hp.cut_max;
     out->device_bytes = static_cast<int64_t>(plan->resident_bytes);
     out->graph_replays = plan->graph_replays;
-    out->weight_unit = plan->hp.delta;
+    out->weight_unit = plan->hp.realw ? 0.0 : plan->hp.delta;
+    out->real_weights = plan->hp.realw ? 1 : 0;
     for (int i = 0; i < 10 && i < qaoa::N_PASS_KINDS; ++i) out->pass_launches[i] = plan->pass_launches[i];
     out->checkpointed_classes = plan->checkpointed_classes;
     out->checkpointed_k_mask = plan->checkpointed_k_mask;

@@ -423,6 +423,62 @@ __device__ __forceinline__ float cgrad_stage(float2 (&f)[A], float2 (&l)[A], uin
     return a;
 }
 
+// Real weights (no common unit, or cut values spanning more than 255 units): the phase of
+// every amplitude comes from its own cut value, exp(-i gamma C(x)).  The table holds
+// C(x) - c0 (c0 the centre of the cone's cut range: a global phase per layer, which no
+// expectation sees, and a smaller argument); the angle gamma (C - c0) / pi is reduced
+// modulo 2 in FP64 and its sine and cosine taken in FP32 (sincospif).
+__device__ __forceinline__ float2 rphase(double gpi, float c) {
+    double x = gpi * static_cast<double>(c);
+    x -= 2.0 * rint(0.5 * x);
+    float sn, cs;
+    sincospif(static_cast<float>(x), &sn, &cs);
+    return make_float2(cs, -sn);
+}
+
+template <int A>
+__device__ __forceinline__ void gen_stage_rw(float2 (&f)[A], const float (&cf)[A], double gpi, float sc) {
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 t = rphase(gpi, cf[r]);
+        f[r] = make_float2(sc * t.x, sc * t.y);
+    }
+}
+
+template <int A>
+__device__ __forceinline__ void phase_stage_rw(float2 (&f)[A], const float (&cf)[A], double gpi, float sc) {
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 t = rphase(gpi, cf[r]);
+        f[r] = cmul(f[r], make_float2(sc * t.x, sc * t.y));
+    }
+}
+
+// Im <lambda| C |psi> with C = cf + c0; then, with UNDO, the conjugate phase scaled by sc.
+template <bool UNDO, int A>
+__device__ __forceinline__ float cgrad_stage_rw(float2 (&f)[A], float2 (&l)[A], const float (&cf)[A], double gpi,
+                                                float c0, float sc) {
+    float a = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        cacc(a, cf[r] + c0, l[r], f[r]);
+        if constexpr (UNDO) {
+            const float2 t0 = rphase(gpi, cf[r]);
+            const float2 t = make_float2(sc * t0.x, sc * t0.y);
+            f[r] = cmulc(f[r], t);
+            l[r] = cmulc(l[r], t);
+        }
+    }
+    return a;
+}
+
+template <int K, int G, int ST, int A>
+__device__ __forceinline__ void load_cuts_rw(float (&cf)[A], const float* cut, uint32_t tau) {
+    const float* cb = cut + tbase<K, G, ST>(tau);
+#pragma unroll
+    for (int r = 0; r < A; ++r) cf[r] = cb[roff<K, G, ST>(r)];
+}
+
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F&& f) {
     if constexpr (B < E) {
@@ -511,7 +567,8 @@ __device__ __forceinline__ double item_sum(double x, double* red, int tid) {
 // layer p-1 ends in stage 0 (qubits 0 and 1).  With ODD the first layer is descending and
 // is peeled off; the remaining layers come in (ascending, descending) pairs, so no branch
 // ever selects between the two layer bodies.
-template <int K, bool GRAD, bool ODD, bool DB, bool GR>
+// RW: real weights (cut_tables then holds float C(x) - c0 per cone; no phase rows).
+template <int K, bool GRAD, bool ODD, bool DB, bool GR, bool RW = false>
 __global__ void __launch_bounds__((Fz<(K >= 3 ? K - 1 : K), (GRAD ? 1 : 0)>::WG))
 k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         const uint8_t* __restrict__ cut_tables, int32_t rowcap, EvalArgs ea) {
@@ -524,7 +581,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     using C = Fz<KL, GI>;
     constexpr int A = C::A;
     __shared__ float2 xbuf[C::S > 1 ? (DB ? 2 : 1) * C::IPW * C::NPAD : 1];
-    __shared__ __attribute__((aligned(16))) uint8_t cutl[C::IPW * C::N < 16 ? 16 : C::IPW * C::N];
+    // cut table of each item: bytes (C - cut_min) or, with RW, floats (C - c0)
+    constexpr int CUTB = (RW ? 4 : 1) * C::IPW * C::N;
+    __shared__ __attribute__((aligned(16))) uint8_t cutl[CUTB < 16 ? 16 : CUTB];
     __shared__ double red[C::WG / 64];
     extern __shared__ float2 prow_all[];   // [IPW][p][rowcap] phase rows of every layer
 
@@ -539,7 +598,12 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     const int point = static_cast<int>(item - slot * P);
     const ConeDev cd = cones[slot];
 
-    {   // the cone's cut table -> LDS (each thread copies A bytes)
+    if constexpr (RW) {   // the cone's float cut table -> LDS (each thread copies A floats)
+        const float* src = reinterpret_cast<const float*>(cut_tables) + cd.cut_off + static_cast<size_t>(tau) * A;
+        float* dst = reinterpret_cast<float*>(cutl) + il * C::N + tau * A;
+#pragma unroll
+        for (int j = 0; j < A; ++j) dst[j] = src[j];
+    } else {   // the cone's cut table -> LDS (each thread copies A bytes)
         const uint8_t* src = cut_tables + cd.cut_off + static_cast<size_t>(tau) * A;
         uint8_t* dst = cutl + il * C::N + tau * A;
         if constexpr (A >= 16) {
@@ -552,6 +616,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         }
     }
     const uint8_t* cut = cutl + il * C::N;
+    const float* cutf = reinterpret_cast<const float*>(cutl) + il * C::N;
     float2* xb = xbuf + (C::S > 1 ? il * C::NPAD : 0);
     float2* xb2 = DB ? xbuf + (C::S > 1 ? (C::IPW + il) * C::NPAD : 0) : nullptr;
     const size_t ipt = static_cast<size_t>(cd.inst) * P + point;   // angle point of the cone's instance
@@ -560,7 +625,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     // phase rows of every layer for this item: prow[il][l][c] = exp(-i gamma_l (cut_min + c)),
     // staged in LDS; GR: they do not fit beside the kernel's LDS (deep circuits with many
     // items per workgroup) and are read from the table in device memory instead
-    if constexpr (!GR) {
+    if constexpr (!GR && !RW) {
         float2* dst = prow_all + static_cast<size_t>(il) * p * rowcap;
         for (int l = 0; l < p; ++l)
             for (int c = static_cast<int>(tau); c < cd.cut_range; c += C::TPI)
@@ -572,9 +637,19 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     constexpr int SL = C::S - 1;
     constexpr int NW = (A + 3) / 4;
     __syncthreads();
-    uint32_t pk0[NW], pkL[NW];
-    load_cuts<KL, GI, 0, A>(pk0, cut, tau);
-    load_cuts<KL, GI, SL, A>(pkL, cut, tau);
+    // cut values of the thread's amplitudes in stages 0 and SL: packed bytes, or floats (RW)
+    uint32_t pk0[RW ? 1 : NW], pkL[RW ? 1 : NW];
+    float cf0[RW ? A : 1], cfL[RW ? A : 1];
+    if constexpr (RW) {
+        load_cuts_rw<KL, GI, 0, A>(cf0, cutf, tau);
+        load_cuts_rw<KL, GI, SL, A>(cfL, cutf, tau);
+    } else {
+        load_cuts<KL, GI, 0, A>(pk0, cut, tau);
+        load_cuts<KL, GI, SL, A>(pkL, cut, tau);
+    }
+    // gamma_l / pi of this item's point (real weights)
+    const double* gam = RW ? ea.gamma + (static_cast<size_t>(cd.inst) * ea.gamma_P + point) * p : nullptr;
+    auto GPI = [&](int l) { return gam[l] * 0.31830988618379067154; };
     // mix0[l] = (tau_l, |kappa_l|^2); a full factored layer scales the state by
     // 1/|kappa|^K, the truncated last layer (qubits 0, 1) by 1/|kappa_p|^2.
     auto kpowK = [&](float k2) { return exp2f(0.5f * K * log2f(k2)); };
@@ -586,23 +661,27 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     // last one also by |kappa_p|^2, so psi leaves the final mixer normalised.
     {
         const float sc = exp2f(-0.5f * K) * (p == 1 ? k2p : 1.f);
-        if constexpr (ODD) gen_stage(f, pkL, ROW(0), sc);
+        if constexpr (RW) gen_stage_rw(f, ODD ? cfL : cf0, GPI(0), sc);
+        else if constexpr (ODD) gen_stage(f, pkL, ROW(0), sc);
         else gen_stage(f, pk0, ROW(0), sc);
     }
     int l1 = 1;
     if constexpr (ODD) {
         const float2 tk = mix0[0];
         fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tk.x);
-        phase_stage(f, pk0, ROW(1), kpowK(tk.y) * (p == 2 ? k2p : 1.f));
+        if constexpr (RW) phase_stage_rw(f, cf0, GPI(1), kpowK(tk.y) * (p == 2 ? k2p : 1.f));
+        else phase_stage(f, pk0, ROW(1), kpowK(tk.y) * (p == 2 ? k2p : 1.f));
         l1 = 2;
     }
     for (; l1 + 1 <= p - 1; l1 += 2) {
         const float2 ta = mix0[l1 - 1];
         fwd_layer<KL, GI, false, FLIP>(f, xb, tau, ta.x);
-        phase_stage(f, pkL, ROW(l1), kpowK(ta.y));
+        if constexpr (RW) phase_stage_rw(f, cfL, GPI(l1), kpowK(ta.y));
+        else phase_stage(f, pkL, ROW(l1), kpowK(ta.y));
         const float2 tb = mix0[l1];
         fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tb.x);
-        phase_stage(f, pk0, ROW(l1 + 1), kpowK(tb.y) * (l1 + 2 == p ? k2p : 1.f));
+        if constexpr (RW) phase_stage_rw(f, cf0, GPI(l1 + 1), kpowK(tb.y) * (l1 + 2 == p ? k2p : 1.f));
+        else phase_stage(f, pk0, ROW(l1 + 1), kpowK(tb.y) * (l1 + 2 == p ? k2p : 1.f));
     }
 
     // ---- last layer: mixer on qubits 0, 1 (register bits 0, 1 of stage 0); <Z0 Z1>
@@ -654,13 +733,17 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         int ly = p;
         for (;;) {
             if (ly == 1) {
-                const float a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
+                float a;
+                if constexpr (RW) a = cgrad_stage_rw<false>(f, lam, cf0, 0.0, cd.c0, 1.f);
+                else a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
                 const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[0] = gc;
                 break;
             }
             {
-                const float a = cgrad_stage<true>(f, lam, pk0, ROW(ly - 1), cd.cut_min, mu);
+                float a;
+                if constexpr (RW) a = cgrad_stage_rw<true>(f, lam, cf0, GPI(ly - 1), cd.c0, mu);
+                else a = cgrad_stage<true>(f, lam, pk0, ROW(ly - 1), cd.cut_min, mu);
                 const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
             }
@@ -673,13 +756,17 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             }
             --ly;
             if (ly == 1) {
-                const float a = cgrad_stage<false>(f, lam, pkL, ROW(0), cd.cut_min, 1.f);
+                float a;
+                if constexpr (RW) a = cgrad_stage_rw<false>(f, lam, cfL, 0.0, cd.c0, 1.f);
+                else a = cgrad_stage<false>(f, lam, pkL, ROW(0), cd.cut_min, 1.f);
                 const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[0] = gc;
                 break;
             }
             {
-                const float a = cgrad_stage<true>(f, lam, pkL, ROW(ly - 1), cd.cut_min, mu);
+                float a;
+                if constexpr (RW) a = cgrad_stage_rw<true>(f, lam, cfL, GPI(ly - 1), cd.c0, mu);
+                else a = cgrad_stage<true>(f, lam, pkL, ROW(ly - 1), cd.cut_min, mu);
                 const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
             }
@@ -721,6 +808,11 @@ hipError_t launch_v(dim3 grid, dim3 block, size_t dyn, const ConeDev* cones, int
     constexpr size_t LDS_MAX = 160 * 1024;
     size_t lds = 0;
     hipError_t e;
+    if (ea.realw) {   // real weights: phases per amplitude, no rows in LDS
+        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, false, true>), grid, block, 0, st, cones, item_base,
+                           n_items, cut, 0, ea);
+        return hipGetLastError();
+    }
     if constexpr (GRAD && K >= 13) {
         if ((e = static_lds<K, GRAD, ODD, true, false>(lds)) != hipSuccess) return e;
         if (lds + dyn <= LDS_MAX) {

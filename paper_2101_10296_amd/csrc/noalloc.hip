@@ -113,7 +113,10 @@ qaoa_status run_energy_grad_noalloc(qaoa_plan_s* P, int64_t n_points, const doub
             NCHECK(launch_tables(gamma + src, beta + src, pc * p, R, hp.cut_min, P->d_inst_delta + j, pc * p,
                                  phase + dst * R, mix + dst, stream));
         }
-        const EvalArgs ea{static_cast<int32_t>(pc), p, M, R, phase, mix, zz, g};
+        // real weights read the angles directly: point i of the chunk is row i0 + i of its
+        // instance's block of n_points
+        const EvalArgs ea{static_cast<int32_t>(pc), p, M, R, phase, mix, gamma + static_cast<size_t>(i0) * p,
+                          static_cast<int32_t>(n_points), hp.realw ? 1 : 0, zz, g};
         for (const auto& grp : P->lds_groups)
             NCHECK(launch_fused(grp.K, true, P->d_cones + grp.first, 0, grp.count * pc, P->d_cut, grp.rowcap, ea,
                                 stream));

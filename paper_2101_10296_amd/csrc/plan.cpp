@@ -90,7 +90,21 @@ int64_t rational_denominator(double x, int64_t qmax, double tol) {
 // Weights become integers wi in units of delta (w = delta * wi): the kernels keep cut
 // values as small integers.  Integer weights use delta = 1; otherwise every weight must be
 // a rational with a denominator of at most 2^20 (to 1e-13 relative), delta = g / L with L
-// the least common denominator and g the gcd of the scaled weights.
+// the least common denominator and g the gcd of the scaled weights.  Weights without such
+// a unit (irrational ones, Gaussian couplings, ...) make the plan one of real weights.
+void weight_units(HostPlan& P);
+
+bool weight_units_or_real(HostPlan& P) {
+    try {
+        weight_units(P);
+        return false;
+    } catch (const PlanError&) {
+        P.wi.assign(P.w.size(), 0);
+        P.delta = 1.0;
+        return true;
+    }
+}
+
 void weight_units(HostPlan& P) {
     const int64_t m = static_cast<int64_t>(P.w.size());
     P.wi.assign(m, 1);
@@ -162,7 +176,7 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
             if (x != 1.0) P.unit = false;
         }
     }
-    weight_units(P);
+    P.realw = weight_units_or_real(P);
     EdgeIndex index;
     index.build(n, P.u, P.v);
     for (int64_t i = 1; i < m; ++i)
@@ -227,6 +241,7 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
     std::vector<int64_t> fail_at(static_cast<size_t>(nt), -1);
     std::vector<PlanError> fail_err(static_cast<size_t>(nt));
     std::vector<char> no_mem(static_cast<size_t>(nt), 0);
+    std::vector<char> wide(static_cast<size_t>(nt), 0);   // a cone's integer cut range above 255
     auto extract_range = [&](int64_t t) {
         std::vector<int32_t> mark(n, -1), dist(n, 0), loc(n, -1), ball;
         ball.reserve(static_cast<size_t>(kmax) + 1);
@@ -277,6 +292,8 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
             c.ea.reserve(ne);
             c.eb.reserve(ne);
             c.ew.reserve(ne);
+            c.wf.reserve(ne);
+            double fmin = 0.0, fmax = 0.0;
             for (int32_t i = 0; i < c.k; ++i) {
                 const int32_t x = ball[i];
                 for (int64_t j = off[x]; j < off[x + 1]; ++j) {
@@ -285,19 +302,19 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
                         c.ea.push_back(i);
                         c.eb.push_back(loc[y]);
                         const int32_t wi = P.wi[nbr_e[j]];
+                        const double wr = P.w[nbr_e[j]];
                         c.ew.push_back(wi);
+                        c.wf.push_back(wr);
                         if (wi < 0) cmin += wi; else cmax += wi;
+                        if (wr < 0) fmin += wr; else fmax += wr;
                     }
                 }
             }
-            if (cmax - cmin > 255) {
-                fail_at[t] = o;
-                fail_err[t] = PlanError{kECONE, "cut values of the cone of orbit " + std::to_string(o) +
-                                                    " span more than 255 integers"};
-                return;
-            }
-            c.cut_min = static_cast<int32_t>(cmin);
-            c.cut_max = static_cast<int32_t>(cmax);
+            if (cmax - cmin > 255) wide[t] = 1;   // integer cut tables hold bytes: real weights instead
+            c.cut_min = static_cast<int32_t>(std::max<int64_t>(cmin, INT32_MIN));
+            c.cut_max = static_cast<int32_t>(std::min<int64_t>(cmax, INT32_MAX));
+            c.cf_min = fmin;
+            c.cf_max = fmax;
         }
     };
     // an allocation failure on a worker thread is carried to the caller's thread
@@ -329,11 +346,22 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
         if (no_mem[t]) throw std::bad_alloc();
     for (int64_t t = 0; t < nt; ++t)
         if (fail_at[t] >= 0) throw fail_err[t];   // ranges are ascending: the first is the lowest
+    for (int64_t t = 0; t < nt; ++t) P.realw = P.realw || wide[t];
     P.cut_min = 0;
     P.cut_max = 0;
-    for (const Cone& c : P.cones) {
-        P.cut_min = std::min<int32_t>(P.cut_min, c.cut_min);
-        P.cut_max = std::max<int32_t>(P.cut_max, c.cut_max);
+    if (P.realw) {
+        P.delta = 1.0;
+        for (int64_t o = 0; o < M; ++o)
+            if (P.cones[o].k > opt.k_lds_max)
+                fail(kECONE, "light cone of orbit " + std::to_string(o) + " has " + std::to_string(P.cones[o].k) +
+                                 " qubits: cones held in device memory need weights with a common unit whose cut "
+                                 "values span at most 255 units (real weights are evaluated for cones of at most " +
+                                 std::to_string(opt.k_lds_max) + " qubits)");
+    } else {
+        for (const Cone& c : P.cones) {
+            P.cut_min = std::min<int32_t>(P.cut_min, c.cut_min);
+            P.cut_max = std::max<int32_t>(P.cut_max, c.cut_max);
+        }
     }
     P.n_inst = 1;
     P.inst_node = {0, n};
@@ -383,6 +411,7 @@ void merge_host_plans(std::vector<HostPlan>& parts, HostPlan& P) {
         P.cut_min = std::min(P.cut_min, h.cut_min);
         P.cut_max = std::max(P.cut_max, h.cut_max);
         P.unit = P.unit && h.unit;
+        P.realw = P.realw || h.realw;
         if (h.delta != P.delta) P.delta = 0.0;   // no single unit: see inst_delta
         P.inst_node.push_back(P.n);
         P.inst_edge.push_back(P.m);
@@ -391,6 +420,17 @@ void merge_host_plans(std::vector<HostPlan>& parts, HostPlan& P) {
         h = HostPlan{};
     }
     if (static_cast<int64_t>(P.rep.size()) > INT32_MAX) fail(kEINVAL, "more than 2^31 - 1 orbits in all");
+    if (P.realw) {
+        // one instance with real weights: every cone takes the real-weight path (a launch
+        // covers cones of all instances), weights used as they are
+        P.delta = 1.0;
+        P.cut_min = P.cut_max = 0;
+        std::fill(P.inst_delta.begin(), P.inst_delta.end(), 1.0);
+        for (size_t o = 0; o < P.cones.size(); ++o)
+            if (P.cones[o].k > 14)
+                fail(kECONE, "light cone of orbit " + std::to_string(o) + " has " + std::to_string(P.cones[o].k) +
+                                 " qubits: with real weights in a batch, every cone must have at most 14 qubits");
+    }
 }
 
 }  // namespace qaoa

@@ -18,8 +18,10 @@ struct Cone {
     int32_t k = 0;                         // qubits
     std::vector<int32_t> nodes;            // graph node of each qubit (u, v, then by (dist, id))
     std::vector<int32_t> ea, eb;           // induced edges as qubit pairs, ea < eb
-    std::vector<int32_t> ew;               // integer weight of each induced edge
-    int32_t cut_min = 0, cut_max = 0;      // range of the cut value C(x) over all x
+    std::vector<int32_t> ew;               // integer weight of each induced edge (units of delta)
+    std::vector<double> wf;                // real weight of each induced edge
+    int32_t cut_min = 0, cut_max = 0;      // range of the cut value C(x) over all x (units of delta)
+    double cf_min = 0.0, cf_max = 0.0;     // the same range in real weights
     int32_t inst = 0;                      // instance (graph) of a plan over several graphs
 };
 
@@ -31,6 +33,10 @@ struct HostPlan {
     std::vector<int32_t> wi;               // weights in units of delta (integers)
     double delta = 1.0;                    // weight unit: w = delta * wi exactly
     bool unit = true;
+    // real weights: no common unit (or a cone's cut values span more than 255 units): cut
+    // values are real numbers, the phase of every amplitude is computed from its own cut
+    // value (workgroup-resident cones only); delta = 1 and wi are unused
+    bool realw = false;
     std::vector<int32_t> edge_orbit;       // [m]
     std::vector<int64_t> rep, size;        // [M]
     std::vector<double> W;                 // [M] orbit weight = sum of member weights

@@ -177,6 +177,7 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
     const int64_t M = static_cast<int64_t>(ord.size());
     std::vector<ConeDev> cd(M);
     std::vector<int32_t> ea, eb, ew;
+    std::vector<double> ewd;   // real weights (plans with real weights only)
     int64_t cut_bytes = 0;
     P->lds_groups.clear();
     for (int64_t s = 0; s < M; ++s) {
@@ -186,12 +187,25 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         d.k = c.k;
         d.edge_off = static_cast<int32_t>(ea.size());
         d.n_edges = static_cast<int32_t>(c.ea.size());
-        d.cut_off = cut_bytes;
-        d.cut_shift = c.cut_min - hp.cut_min;
-        d.cut_min = c.cut_min;
-        d.cut_range = c.cut_max - c.cut_min + 1;
         d.inst = c.inst;
-        cut_bytes += std::max<int64_t>(int64_t{1} << c.k, 16);
+        d.c0 = 0.f;
+        d.pad_ = 0;
+        if (hp.realw) {
+            // float table of C(x) - c0 over the stored half; cut_off counts floats
+            d.cut_off = cut_bytes / 4;
+            d.cut_shift = 0;
+            d.cut_min = 0;
+            d.cut_range = 1;
+            d.c0 = static_cast<float>(0.5 * (c.cf_min + c.cf_max));
+            cut_bytes += 4 * std::max<int64_t>(int64_t{1} << (c.k >= 3 ? c.k - 1 : c.k), 4);
+            ewd.insert(ewd.end(), c.wf.begin(), c.wf.end());
+        } else {
+            d.cut_off = cut_bytes;
+            d.cut_shift = c.cut_min - hp.cut_min;
+            d.cut_min = c.cut_min;
+            d.cut_range = c.cut_max - c.cut_min + 1;
+            cut_bytes += std::max<int64_t>(int64_t{1} << c.k, 16);
+        }
         ea.insert(ea.end(), c.ea.begin(), c.ea.end());
         eb.insert(eb.end(), c.eb.begin(), c.eb.end());
         ew.insert(ew.end(), c.ew.begin(), c.ew.end());
@@ -270,7 +284,20 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         QCHECK(hipMemcpy(P->d_eb, eb.data(), eb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         QCHECK(hipMemcpy(P->d_ew, ew.data(), ew.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    QCHECK(launch_cut_tables(P->d_cones, M, P->d_ea, P->d_eb, P->d_ew, P->d_cut, nullptr));
+    if (hp.realw) {
+        double* d_ewd = nullptr;
+        QCHECK(hipMalloc(&d_ewd, std::max<size_t>(ewd.size(), 1) * sizeof(double)));
+        hipError_t e1 = ewd.empty() ? hipSuccess
+                                    : hipMemcpy(d_ewd, ewd.data(), ewd.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e1 == hipSuccess)
+            e1 = launch_cut_tables_real(P->d_cones, M, P->d_ea, P->d_eb, d_ewd, reinterpret_cast<float*>(P->d_cut),
+                                        nullptr);
+        if (e1 == hipSuccess) e1 = hipDeviceSynchronize();
+        hipFree(d_ewd);
+        QCHECK(e1);
+    } else {
+        QCHECK(launch_cut_tables(P->d_cones, M, P->d_ea, P->d_eb, P->d_ew, P->d_cut, nullptr));
+    }
     QCHECK(launch_tt_tables(P->d_hcones, static_cast<int64_t>(hc.size()), max_groups, P->d_ea, P->d_eb, P->d_ew,
                             P->d_tt, nullptr));
     QCHECK(hipDeviceSynchronize());
@@ -364,7 +391,8 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
     QCHECK(launch_tables(gamma, beta, static_cast<int64_t>(npl), R, hp.cut_min, P->d_inst_delta,
                          static_cast<int64_t>(n_points) * p, P->d_phase, P->d_mix, stream));
     QCHECK(tm.end());
-    EvalArgs ea{static_cast<int32_t>(n_points), p, M, R, P->d_phase, P->d_mix, zz, g};
+    EvalArgs ea{static_cast<int32_t>(n_points), p, M, R, P->d_phase, P->d_mix, gamma,
+                static_cast<int32_t>(n_points), hp.realw ? 1 : 0, zz, g};
     for (const auto& grp : P->lds_groups) {
         const ConeDev* cones = P->d_cones + grp.first;
         const int64_t items = grp.count * n_points;

@@ -109,6 +109,8 @@ hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, 
                          const double* deltas, int64_t pl_per_inst, float2* phase, float2* mix, hipStream_t st);
 hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
                              const int32_t* ew, uint8_t* tables, hipStream_t st);
+hipError_t launch_cut_tables_real(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
+                                  const double* ew, float* tables, hipStream_t st);
 hipError_t launch_pass(int kind, const PassArgs& pa, hipStream_t st);
 hipError_t launch_tt_tables(const ConeHbm* cones, int64_t n_cones, int max_groups, const int32_t* ea,
                             const int32_t* eb, const int32_t* ew, uint8_t* tt, hipStream_t st);

@@ -103,7 +103,7 @@ def test_weighted_planner_and_weight_preservation():
     (dict(edges=[[0, 1], [1, 0]], n=3), Q.QAOA_EINVAL),
     (dict(edges=[[0, 5]], n=3), Q.QAOA_EINVAL),
     (dict(edges=[[0, 1]], n=3, p=0), Q.QAOA_EINVAL),
-    (dict(edges=[[0, 1], [1, 2]], n=3, weights=[1.0, 2 ** 0.5]), Q.QAOA_EINVAL),
+    (dict(edges=[[0, 1], [1, 2]], n=3, weights=[1.0, float("inf")]), Q.QAOA_EINVAL),
     (dict(edges=[[0, 1], [1, 2]], n=3, weights=[1.0, float("nan")]), Q.QAOA_EINVAL),
     (dict(edges=[[0, 1], [1, 2]], n=3, generators=[[1, 0, 2]]), Q.QAOA_ENOTAUT),
     (dict(edges=[[0, 1], [1, 2]], n=3, generators=[[0, 0, 2]]), Q.QAOA_ENOTAUT),
@@ -137,12 +137,24 @@ def test_weight_unit(w, unit):
     assert info["total_weight"] == pytest.approx(sum(w), rel=1e-15, abs=1e-15)
 
 
-def test_cut_range_limit():
-    # 3 x 3 rook graph with weight 30 per edge: cut values span more than 255 integers
-    g = W.rook(3)
+def test_real_weights():
+    # weights without a common unit, or integer cut values spanning more than 255 units,
+    # plan as real weights (phases from each amplitude's own cut value) for cones of at most
+    # 14 qubits; a larger cone is refused
+    g = W.rook(3)   # 3 x 3 rook graph, weight 30 per edge: cut values span more than 255
+    for w in (np.full(g.m, 30.0), np.random.default_rng(1).normal(size=g.m)):
+        info = Q.Plan(g.n, g.edges, p=1, weights=w).info()
+        assert info["real_weights"] == 1 and info["weight_unit"] == 0.0
+    c = W.circulant(40, (1, 2))
+    d = (c.edges[:, 1] - c.edges[:, 0]) % c.n
+    w = np.where(np.minimum(d, c.n - d) == 1, 1.0, 2 ** 0.5)
+    pl = Q.Plan(c.n, c.edges, p=2, weights=w, generators=c.gens())
+    assert pl.info()["real_weights"] == 1 and pl.info()["n_orbits"] == 2
+    assert Q.Plan(c.n, c.edges, p=2, weights=np.where(w == 1.0, 1.0, 2.0)).info()["real_weights"] == 0
+    s = W.star(15)   # one 16-qubit cone: held in device memory, which needs integer cut values
     with pytest.raises(Q.QaoaError) as ei:
-        Q.Plan(g.n, g.edges, p=1, weights=np.full(g.m, 30.0))
-    assert ei.value.status == Q.QAOA_ECONE
+        Q.Plan(s.n, s.edges, p=1, weights=np.full(s.m, 30.0))
+    assert ei.value.status == Q.QAOA_ECONE and "orbit 0 has 16 qubits" in str(ei.value)
 
 
 def test_empty_and_isolated():
@@ -163,17 +175,16 @@ def test_first_failing_cone_is_reported():
         Q.Plan(g.n, g.edges, p=2, max_cone_qubits=6)
     assert ei.value.status == Q.QAOA_ECONE
     assert f"light cone of orbit {first} " in str(ei.value)
-    # a cut-range failure far into the orbit list: weight 300 on one late edge; the first
-    # cone holding both of its ends fails
+    # weight 300 on one late edge makes the weights real (its cones' cut values span more
+    # than 255): at p = 3 the lowest orbit whose cone is held in device memory is named
     w = np.ones(g.m)
-    x, y = (int(t) for t in g.edges[g.m - 5])
     w[g.m - 5] = 300.0
     with pytest.raises(Q.QaoaError) as ei:
-        Q.Plan(g.n, g.edges, p=1, weights=w)
+        Q.Plan(g.n, g.edges, p=3, weights=w)
     assert ei.value.status == Q.QAOA_ECONE
-    cones = oracle.plan(g.n, g.edges, None, None, 1, reduce=True, max_k=40)["cones"]
-    bad = [m for m, c in enumerate(cones) if x in c["nodes"] and y in c["nodes"]]
-    assert f"cone of orbit {min(bad)} " in str(ei.value)
+    cones = oracle.plan(g.n, g.edges, None, None, 3, reduce=True, max_k=40)["cones"]
+    first = next(m for m, c in enumerate(cones) if c["k"] > 14)
+    assert f"light cone of orbit {first} has " in str(ei.value)
 
 
 def test_batch_plan_concatenates_instances():

@@ -37,7 +37,7 @@ def check_energy(Q, g, p, ga, be, reduce=True, weights=None, grad=False, plan_kw
     E, zz = pl.energy(dev(ga), dev(be), term_zz=True)
     torch.cuda.synchronize()
     E, zz = E.cpu().numpy(), zz.cpu().numpy()
-    Wt = float(np.sum(ref["W"]))
+    Wt = float(np.sum(np.abs(ref["W"])))   # |E_gpu - E| <= sum_m |W_m| |dzz_m| / 2 (signed weights too)
     if sample is None:
         Eo, zzo = oracle.energy(ref, ga, be)
         assert np.abs(zz - zzo).max() <= ZZ_TOL, np.abs(zz - zzo).max()
@@ -401,3 +401,59 @@ def test_deep_circuits_phase_rows_in_device_memory(Q):
     check_energy(Q, W.single_edge(), 150, ga, be, grad=True)
     ga, be = W.draw_angles(2, 120, 92)
     check_energy(Q, W.triangle(), 120, ga, be, grad=True)
+
+
+def test_real_weights_irrational_with_symmetry(Q):
+    # C_40(1,2) with weight 1 on the step-1 edges and sqrt(2) on the step-2 edges (an Ising
+    # instance with an edge-colour symmetry, Sec. 4): no common unit, so the phase of every
+    # amplitude comes from its own real cut value; the rotation and reflection preserve the
+    # weights, two orbits
+    g = W.circulant(40, (1, 2))
+    d = (g.edges[:, 1] - g.edges[:, 0]) % g.n
+    w = np.where(np.minimum(d, g.n - d) == 1, 1.0, 2 ** 0.5)
+    ga, be = W.draw_angles(5, 2, 41)
+    pl, _, _ = check_energy(Q, g, 2, ga, be, reduce=True, weights=w, grad=True)
+    assert pl.info()["real_weights"] == 1 and pl.info()["n_orbits"] == 2
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_real_weights_gaussian_unreduced(Q, p):
+    # Gaussian couplings (no symmetry survives: every edge its own term), cones of 4-12 qubits
+    g = W.random_regular(12, 3, 21)
+    w = np.random.default_rng(p).normal(size=g.m)
+    ga, be = W.draw_angles(4, p, 42 + p)
+    pl, _, _ = check_energy(Q, g, p, ga, be, reduce=False, weights=w, grad=True)
+    assert pl.info()["real_weights"] == 1
+
+
+def test_real_weights_every_cone_size_and_wide_range(Q):
+    # stars K_{1,m} (one cone of m + 1 = 2..14 qubits, every workgroup kernel size) with
+    # Gaussian weights at p = 2; and integer weights whose cut values span more than 255
+    # units (3 x 3 rook graph, weight 30 per edge), which also take the real-weight path
+    rng = np.random.default_rng(5)
+    for m in range(1, 14):
+        g = W.star(m)
+        ga, be = W.draw_angles(2, 2, 60 + m)
+        check_energy(Q, g, 2, ga, be, reduce=False, weights=rng.normal(size=g.m), grad=True)
+    g = W.rook(3)
+    ga, be = W.draw_angles(3, 2, 44)
+    pl, _, _ = check_energy(Q, g, 2, ga, be, reduce=True, weights=np.full(g.m, 30.0), grad=True)
+    assert pl.info()["real_weights"] == 1
+
+
+def test_real_weights_in_a_batch_and_terms(Q):
+    # a batch plan with one real-weight instance: every instance takes the real-weight path;
+    # each block equals its own plan, and the per-term gradients combine to the gradient
+    g1, g2 = W.random_regular(14, 3, 22), W.circulant(30, (1, 2))
+    w1 = np.random.default_rng(7).normal(size=g1.m)
+    ga, be = W.draw_angles(3, 2, 45)
+    bp = Q.Plan.batch([(g1.n, g1.edges, w1, None), (g2.n, g2.edges, None, g2.gens())], 2)
+    assert bp.info()["real_weights"] == 1
+    E, dg, db, zz, tg = (x.cpu().numpy() for x in bp.energy_grad_terms(dev(ga), dev(be)))
+    for j, (g, w, gens) in enumerate(((g1, w1, None), (g2, None, g2.gens()))):
+        ref = oracle.plan(g.n, g.edges, w, gens, 2, reduce=gens is not None)
+        Eo, dgo, dbo, _ = oracle.energy_grad(ref, ga, be)
+        Wt = float(np.sum(np.abs(ref["W"])))
+        assert np.abs(E[j] - Eo).max() <= ZZ_TOL * Wt / 2
+        scale = max(np.abs(dgo).max(), np.abs(dbo).max(), 1e-3 * Wt)
+        assert max(np.abs(dg[j] - dgo).max(), np.abs(db[j] - dbo).max()) <= 1e-4 * scale
