@@ -112,6 +112,16 @@ typedef struct {
                                      replay the graph on the caller's stream (angle values may
                                      change in place between calls).  Not with profile or
                                      one_cone_at_a_time. */
+    int32_t tune;                 /* 1 = run-time tuning: the first call that needs a kernel class
+                                     times its layout choices on the device (workgroup-resident
+                                     cones: register bits per LDS stage and workgroup size;
+                                     cones in device memory: tiles per workgroup) and keeps the
+                                     fastest for the rest of the process, per (device
+                                     architecture, class, k, p, gradient, real weights);
+                                     qaoa_tuning_report lists the choices.  0 = fixed defaults;
+                                     2, 3, 4 = workgroup layout 0 (default), 1 (one register bit
+                                     fewer per stage), 2 (workgroups of >= 256 threads) wherever
+                                     it applies, without timing (tests, experiments) */
 } qaoa_plan_opts;
 
 typedef struct {
@@ -270,6 +280,15 @@ qaoa_status qaoa_plan_kernel_times(qaoa_plan_t plan, int32_t cap, int32_t* k_out
  * Errors: QAOA_EINVAL for a bad graph (ids, self-loops, duplicate edges) or limits. */
 qaoa_status qaoa_find_generators(const qaoa_problem* pr, int32_t max_generators, double time_limit_s,
                                  int32_t* generators, int32_t* n_found, int32_t* complete);
+
+/* The run-time tuner's choices so far in this process (plans built with opts.tune = 1), one
+ * line per kernel class: device architecture, class, k, p, gradient, real weights, the
+ * chosen layout and the milliseconds measured for every candidate.  Writes at most cap - 1
+ * characters and a terminating zero into buf (caller-owned host memory, may be NULL when
+ * cap is 0); *len = the length of the whole report.  The tuner serves the batching and
+ * scheduling of the light-cone evaluations (Sec. 2.3 terms are independent work items).
+ * Errors: EINVAL (NULL len). */
+qaoa_status qaoa_tuning_report(char* buf, int64_t cap, int64_t* len);
 
 /* Release the plan and everything it owns on the device (synchronises the device). */
 void qaoa_plan_destroy(qaoa_plan_t plan);

@@ -19,7 +19,7 @@ from . import _capi
 from ._capi import (QAOA_EHIP, QAOA_ECONE, QAOA_EINVAL, QAOA_ENOMEM, QAOA_ENOTAUT,  # noqa: F401
                     QAOA_OK, STATUS_NAMES)
 
-__all__ = ["Plan", "QaoaError", "qaoa_energy", "QAOAEnergyFn", "library_path"]
+__all__ = ["Plan", "QaoaError", "qaoa_energy", "QAOAEnergyFn", "library_path", "tuning_report", "find_generators"]
 
 
 def library_path() -> str:
@@ -69,7 +69,7 @@ class Plan:
     def __init__(self, n_nodes: int, edges, p: int, weights=None, generators=None, *, reduce: bool = True,
                  max_cone_qubits: int = 30, k_lds_max: int = 14, mem_budget_bytes: int = 0,
                  checkpoint_mode: int = 0, one_cone_at_a_time: bool = False, profile: bool = False,
-                 graph: bool = False, _instances=None):
+                 graph: bool = False, tune: bool = False, _instances=None):
         L = _capi.lib()
         o = _capi.PlanOpts()
         L.qaoa_plan_opts_default(C.byref(o))
@@ -81,6 +81,7 @@ class Plan:
         o.one_cone_at_a_time = int(bool(one_cone_at_a_time))
         o.profile = int(bool(profile))
         o.graph = int(bool(graph))
+        o.tune = int(tune)
         keep = []
         h = C.c_void_p()
         if _instances is None:
@@ -244,6 +245,16 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def tuning_report() -> str:
+    """The run-time tuner's choices so far in this process (plans built with tune=True)."""
+    L = _capi.lib()
+    n = C.c_int64()
+    _check(L.qaoa_tuning_report(None, 0, C.byref(n)))
+    buf = C.create_string_buffer(n.value + 1)
+    _check(L.qaoa_tuning_report(buf, n.value + 1, C.byref(n)))
+    return buf.value.decode()
 
 
 def find_generators(n_nodes: int, edges, weights=None, max_generators: int = 256, time_limit: float = 30.0):

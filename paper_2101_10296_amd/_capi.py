@@ -22,7 +22,7 @@ class Problem(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("reduce", C.c_int32), ("max_cone_qubits", C.c_int32),
                 ("k_lds_max", C.c_int32), ("checkpoint_mode", C.c_int32), ("one_cone_at_a_time", C.c_int32),
-                ("profile", C.c_int32), ("graph", C.c_int32)]
+                ("profile", C.c_int32), ("graph", C.c_int32), ("tune", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -71,6 +71,8 @@ def lib():
         L.qaoa_find_generators.argtypes = [C.POINTER(Problem), i32, C.c_double, C.POINTER(i32), C.POINTER(i32),
                                            C.POINTER(i32)]
         L.qaoa_find_generators.restype = i32
+        L.qaoa_tuning_report.argtypes = [C.c_char_p, i64, C.POINTER(i64)]
+        L.qaoa_tuning_report.restype = i32
         L.qaoa_plan_destroy.argtypes = [vp]
         L.qaoa_plan_destroy.restype = None
         L.qaoa_last_error.argtypes = []

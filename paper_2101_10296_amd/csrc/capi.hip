@@ -72,6 +72,8 @@ qaoa_status plan_options(const qaoa_plan_opts* opts, qaoa::PlanOptions& o) {
         o.one_cone_at_a_time = opts->one_cone_at_a_time;
         o.profile = opts->profile;
         o.graph = opts->graph;
+        o.tune = opts->tune;
+        if (o.tune < 0 || o.tune > 4) return set_err(QAOA_EINVAL, "tune must be 0, 1 or 2-4");
         if (o.mem_budget_bytes < 0) return set_err(QAOA_EINVAL, "mem_budget_bytes must be >= 0");
         if (o.reduce != 0 && o.reduce != 1) return set_err(QAOA_EINVAL, "reduce must be 0 or 1");
         if (o.graph != 0 && o.graph != 1) return set_err(QAOA_EINVAL, "graph must be 0 or 1");
@@ -229,6 +231,18 @@ qaoa_status qaoa_plan_kernel_times(qaoa_plan_t plan, int32_t cap, int32_t* k_out
     std::string msg;
     const qaoa_status st = qaoa::kernel_times(plan, cap, k_out, items_out, ms_out, n_out, msg);
     if (st != QAOA_OK) return set_err(st, msg);
+    return QAOA_OK;
+}
+
+qaoa_status qaoa_tuning_report(char* buf, int64_t cap, int64_t* len) {
+    if (!len || (cap > 0 && !buf)) return set_err(QAOA_EINVAL, "len is NULL (or buf is NULL with cap > 0)");
+    const std::string r = qaoa::tuning_report();
+    *len = static_cast<int64_t>(r.size());
+    if (cap > 0) {
+        const size_t n = std::min<size_t>(r.size(), static_cast<size_t>(cap - 1));
+        std::memcpy(buf, r.data(), n);
+        buf[n] = 0;
+    }
     return QAOA_OK;
 }
 

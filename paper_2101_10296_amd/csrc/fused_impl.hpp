@@ -37,18 +37,24 @@
 
 namespace qaoa {
 
-// G = 1 for the adjoint kernels, which hold two states and use 16 amplitudes per thread.
+// G bit 0 = 1 for the adjoint kernels, which hold two states and use 16 amplitudes per
+// thread; G >> 1 selects a layout variant for the run-time tuner:
+//   0  the default: 5 register bits per stage forward, 4 adjoint; workgroups of >= 64 threads
+//   1  one register bit fewer per stage (qubits per LDS pass): more threads per item
+//   2  workgroups of >= 256 threads (more cones per workgroup for small cones)
 #ifndef QAOA_FUSED_AB_GRAD
 #define QAOA_FUSED_AB_GRAD 4
 #endif
 template <int K, int G = 0>
 struct Fz {
-    static constexpr int AB_MAX = G ? QAOA_FUSED_AB_GRAD : 5;
+    static constexpr int VAR = G >> 1;
+    static constexpr int AB_MAX = ((G & 1) ? QAOA_FUSED_AB_GRAD : 5) - (VAR == 1 ? 1 : 0);
     static constexpr int AB = K < AB_MAX ? K : AB_MAX;  // register bits
     static constexpr int A = 1 << AB;              // amplitudes per thread per state
     static constexpr int TB = K - AB;              // thread bits per item
     static constexpr int TPI = 1 << TB;            // threads per item
-    static constexpr int WG = TPI > 64 ? TPI : 64;
+    static constexpr int WGMIN = VAR == 2 ? 256 : 64;
+    static constexpr int WG = TPI > WGMIN ? TPI : WGMIN;
     static constexpr int IPW = WG / TPI;           // items per workgroup
     // LQ: K = S * AB + 1, so the one qubit left over (K-1) sits on lane bit 0 in the last
     // stage and is mixed across lanes there instead of costing a stage of its own.
@@ -568,11 +574,11 @@ __device__ __forceinline__ double item_sum(double x, double* red, int tid) {
 // is peeled off; the remaining layers come in (ascending, descending) pairs, so no branch
 // ever selects between the two layer bodies.
 // RW: real weights (cut_tables then holds float C(x) - c0 per cone; no phase rows).
-template <int K, bool GRAD, bool ODD, bool DB, bool GR, bool RW = false>
-__global__ void __launch_bounds__((Fz<(K >= 3 ? K - 1 : K), (GRAD ? 1 : 0)>::WG))
+template <int K, bool GRAD, bool ODD, bool DB, bool GR, bool RW = false, int V = 0>
+__global__ void __launch_bounds__((Fz<(K >= 3 ? K - 1 : K), (GRAD ? 1 : 0) | (V << 1)>::WG))
 k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         const uint8_t* __restrict__ cut_tables, int32_t rowcap, EvalArgs ea) {
-    constexpr int GI = GRAD ? 1 : 0;
+    constexpr int GI = (GRAD ? 1 : 0) | (V << 1);
     // FLIP: the state is stored on KL = K - 1 qubits (global-flip halving); every sum over
     // the stored half is half the sum over the whole state
     constexpr bool FLIP = K >= 3;
@@ -785,13 +791,14 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
 // ---------------------------------------------------------------- launcher
 // LDS bytes a kernel variant declares statically (queried once per variant; concurrent
 // first calls may both query, which is harmless)
-template <int K, bool GRAD, bool ODD, bool DB, bool GR>
+template <int K, bool GRAD, bool ODD, bool DB, bool GR, int V>
 hipError_t static_lds(size_t& out) {
     static std::atomic<size_t> bytes{0};   // + 1 once queried
     size_t b = bytes.load(std::memory_order_relaxed);
     if (!b) {
         hipFuncAttributes fa{};
-        const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, GRAD, ODD, DB, GR>));
+        const hipError_t e =
+            hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_fused<K, GRAD, ODD, DB, GR, false, V>));
         if (e != hipSuccess) return e;
         b = fa.sharedSizeBytes + 1;
         bytes.store(b, std::memory_order_relaxed);
@@ -800,43 +807,54 @@ hipError_t static_lds(size_t& out) {
     return hipSuccess;
 }
 
-// Picks the variant whose LDS holds the phase rows (dyn bytes): two transpose buffers
-// (adjoint, 13 and 14 qubits) when they fit, else one, else rows stay in device memory.
-template <int K, bool GRAD, bool ODD>
+// Picks the kernel whose LDS holds the phase rows (dyn bytes): two transpose buffers
+// (adjoint, 13 and 14 qubits) when they fit, else one, else rows stay in device memory;
+// real weights need no rows.
+template <int K, bool GRAD, bool ODD, int V>
 hipError_t launch_v(dim3 grid, dim3 block, size_t dyn, const ConeDev* cones, int64_t item_base, int64_t n_items,
                     const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
     constexpr size_t LDS_MAX = 160 * 1024;
     size_t lds = 0;
     hipError_t e;
     if (ea.realw) {   // real weights: phases per amplitude, no rows in LDS
-        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, false, true>), grid, block, 0, st, cones, item_base,
+        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, false, true, V>), grid, block, 0, st, cones, item_base,
                            n_items, cut, 0, ea);
         return hipGetLastError();
     }
     if constexpr (GRAD && K >= 13) {
-        if ((e = static_lds<K, GRAD, ODD, true, false>(lds)) != hipSuccess) return e;
+        if ((e = static_lds<K, GRAD, ODD, true, false, V>(lds)) != hipSuccess) return e;
         if (lds + dyn <= LDS_MAX) {
-            hipLaunchKernelGGL((k_fused<K, GRAD, ODD, true, false>), grid, block, dyn, st, cones, item_base, n_items,
-                               cut, rowcap, ea);
+            hipLaunchKernelGGL((k_fused<K, GRAD, ODD, true, false, false, V>), grid, block, dyn, st, cones, item_base,
+                               n_items, cut, rowcap, ea);
             return hipGetLastError();
         }
     }
-    if ((e = static_lds<K, GRAD, ODD, false, false>(lds)) != hipSuccess) return e;
+    if ((e = static_lds<K, GRAD, ODD, false, false, V>(lds)) != hipSuccess) return e;
     if (lds + dyn <= LDS_MAX)
-        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, false>), grid, block, dyn, st, cones, item_base, n_items,
-                           cut, rowcap, ea);
+        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, false, false, V>), grid, block, dyn, st, cones, item_base,
+                           n_items, cut, rowcap, ea);
     else
-        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, true>), grid, block, 0, st, cones, item_base, n_items, cut,
-                           -1, ea);
+        hipLaunchKernelGGL((k_fused<K, GRAD, ODD, false, true, false, V>), grid, block, 0, st, cones, item_base,
+                           n_items, cut, -1, ea);
     return hipGetLastError();
 }
 
+// Variants of the K-qubit kernel that differ from the default layout (Fz): 1 needs more
+// stored qubits than the default register bits minus one, 2 fewer threads per item than 256.
 template <int K>
-hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
-                           const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
+constexpr bool fused_variant_ok(bool grad, int v) {
+    constexpr int KL = K >= 3 ? K - 1 : K;
+    if (v == 0) return true;
+    if (v == 1) return grad ? KL >= QAOA_FUSED_AB_GRAD : KL >= 5;
+    return grad ? Fz<KL, 1>::TPI < 256 : Fz<KL, 0>::TPI < 256;
+}
+
+template <int K, int V>
+hipError_t launch_kv(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items, const uint8_t* cut,
+                     int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
     constexpr int KL = K >= 3 ? K - 1 : K;   // stored qubits (global-flip halving)
-    const int ipw = grad ? Fz<KL, 1>::IPW : Fz<KL, 0>::IPW;
-    const int wg = grad ? Fz<KL, 1>::WG : Fz<KL, 0>::WG;
+    const int ipw = grad ? Fz<KL, 1 | (V << 1)>::IPW : Fz<KL, V << 1>::IPW;
+    const int wg = grad ? Fz<KL, 1 | (V << 1)>::WG : Fz<KL, V << 1>::WG;
     const int64_t todo = n_items - item_base;
     const int64_t blocks = (todo + ipw - 1) / ipw;
     if (blocks <= 0) return hipSuccess;
@@ -850,14 +868,29 @@ hipError_t launch_k(bool grad, const ConeDev* cones, int64_t item_base, int64_t 
         const int64_t base = item_base + b0 * ipw;
         hipError_t e;
         if (grad)
-            e = odd ? launch_v<K, true, true>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
-                    : launch_v<K, true, false>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
+            e = odd ? launch_v<K, true, true, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
+                    : launch_v<K, true, false, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
         else
-            e = odd ? launch_v<K, false, true>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
-                    : launch_v<K, false, false>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
+            e = odd ? launch_v<K, false, true, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
+                    : launch_v<K, false, false, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// variant: 0, 1, 2 (see Fz); a variant that does not apply to K runs the default
+template <int K>
+hipError_t launch_k(bool grad, int variant, const ConeDev* cones, int64_t item_base, int64_t n_items,
+                    const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
+    if (variant == 1 && fused_variant_ok<K>(grad, 1)) {
+        if constexpr ((K >= 3 ? K - 1 : K) >= QAOA_FUSED_AB_GRAD)
+            return launch_kv<K, 1>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+    }
+    if (variant == 2 && fused_variant_ok<K>(grad, 2)) {
+        if constexpr (Fz<(K >= 3 ? K - 1 : K), 0>::TPI < 256)
+            return launch_kv<K, 2>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+    }
+    return launch_kv<K, 0>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
 }
 
 }  // namespace qaoa

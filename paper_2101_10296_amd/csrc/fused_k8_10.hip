@@ -3,19 +3,19 @@
 
 namespace qaoa {
 
-hipError_t launch_fused_k8(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+hipError_t launch_fused_k8(bool grad, int variant, const ConeDev* cones, int64_t item_base, int64_t n_items,
                           const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
-    return launch_k<8>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+    return launch_k<8>(grad, variant, cones, item_base, n_items, cut, rowcap, ea, st);
 }
 
-hipError_t launch_fused_k9(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+hipError_t launch_fused_k9(bool grad, int variant, const ConeDev* cones, int64_t item_base, int64_t n_items,
                           const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
-    return launch_k<9>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+    return launch_k<9>(grad, variant, cones, item_base, n_items, cut, rowcap, ea, st);
 }
 
-hipError_t launch_fused_k10(bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+hipError_t launch_fused_k10(bool grad, int variant, const ConeDev* cones, int64_t item_base, int64_t n_items,
                           const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
-    return launch_k<10>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+    return launch_k<10>(grad, variant, cones, item_base, n_items, cut, rowcap, ea, st);
 }
 
 }  // namespace qaoa

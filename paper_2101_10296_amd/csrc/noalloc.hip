@@ -118,8 +118,8 @@ qaoa_status run_energy_grad_noalloc(qaoa_plan_s* P, int64_t n_points, const doub
         const EvalArgs ea{static_cast<int32_t>(pc), p, M, R, phase, mix, gamma + static_cast<size_t>(i0) * p,
                           static_cast<int32_t>(n_points), hp.realw ? 1 : 0, zz, g};
         for (const auto& grp : P->lds_groups)
-            NCHECK(launch_fused(grp.K, true, P->d_cones + grp.first, 0, grp.count * pc, P->d_cut, grp.rowcap, ea,
-                                stream));
+            NCHECK(launch_fused(grp.K, true, 0, P->d_cones + grp.first, 0, grp.count * pc, P->d_cut, grp.rowcap,
+                                ea, stream));   // default layout: no tuning runs here
         NCHECK(launch_combine(P->d_W, zz, g, M, p, P->d_inst_orbit, P->d_inst_delta, ni, pc, n_points, i0, energy,
                               dgamma, dbeta, stream));
     }

@@ -61,6 +61,7 @@ struct PlanOptions {
     int32_t one_cone_at_a_time = 0;
     int32_t profile = 0;
     int32_t graph = 0;
+    int32_t tune = 0;
 };
 
 // Throws PlanError on invalid input.

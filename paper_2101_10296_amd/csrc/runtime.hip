@@ -3,11 +3,93 @@
 #include "runtime.hpp"
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 
 namespace qaoa {
 namespace {
+
+// ---- run-time tuner (plans built with opts.tune = 1).  Layout choices of a kernel class
+// are timed once per process on the first call that needs them (HIP events on the call's
+// stream) and the fastest is kept, keyed by (device architecture, what, k, p, gradient,
+// real weights).  what = 0: register bits per LDS stage / workgroup size of the
+// workgroup-resident kernel (fused_variants); what = 1: tiles per workgroup of the
+// device-memory passes.
+struct TuneKey {
+    std::string arch;
+    int what, k, p, grad, realw;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, what, k, p, grad, realw) < std::tie(o.arch, o.what, o.k, o.p, o.grad, o.realw);
+    }
+};
+struct TuneRec {
+    int choice = 0;
+    std::vector<std::pair<int, float>> ms;   // candidate -> milliseconds per timed launch
+    int64_t items = 0;                       // items of the timed launches
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneRec> g_tune;
+
+std::string device_arch(int dev) {
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop{};
+    std::string a = hipGetDeviceProperties(&prop, dev) == hipSuccess ? std::string(prop.gcnArchName) : "unknown";
+    names[dev] = a;
+    return a;
+}
+
+bool tune_lookup(const TuneKey& key, int& choice) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    choice = it->second.choice;
+    return true;
+}
+
+// Times run(candidate) for every candidate (one untimed launch, then `reps` timed ones on
+// the stream) and records the fastest under key.
+template <class Run>
+hipError_t tune_pick(const TuneKey& key, const std::vector<int>& cand, int64_t items, hipStream_t st, Run&& run,
+                     int& choice) {
+    TuneRec rec;
+    rec.items = items;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    constexpr int reps = 3;
+    float best = 0.f;
+    for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
+        e = run(cand[i]);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; e == hipSuccess && r < reps; ++r) e = run(cand[i]);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        ms /= reps;
+        rec.ms.emplace_back(cand[i], ms);
+        if (i == 0 || ms < best) {
+            best = ms;
+            rec.choice = cand[i];
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    choice = rec.choice;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = rec;
+    return hipSuccess;
+}
 
 #define QCHECK(expr)                                                               \
     do {                                                                           \
@@ -393,15 +475,32 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
     QCHECK(tm.end());
     EvalArgs ea{static_cast<int32_t>(n_points), p, M, R, P->d_phase, P->d_mix, gamma,
                 static_cast<int32_t>(n_points), hp.realw ? 1 : 0, zz, g};
+    const std::string arch = P->opt.tune == 1 ? device_arch(P->device) : std::string();
     for (const auto& grp : P->lds_groups) {
         const ConeDev* cones = P->d_cones + grp.first;
         const int64_t items = grp.count * n_points;
+        int variant = P->opt.tune >= 2 ? P->opt.tune - 2 : 0;   // tune 2, 3, 4: a fixed layout variant
+        if (P->opt.tune == 1 && !P->opt.one_cone_at_a_time) {
+            const TuneKey key{arch, 0, grp.K, p, grad ? 1 : 0, hp.realw ? 1 : 0};
+            if (!tune_lookup(key, variant)) {
+                const std::vector<int> cand = fused_variants(grp.K, grad);
+                if (cand.size() <= 1 || fixed_batches) {
+                    variant = 0;
+                } else {
+                    // timed on up to 2^16 items of this call (their results are written again below)
+                    const int64_t ns = std::min<int64_t>(items, int64_t{1} << 16);
+                    QCHECK(tune_pick(key, cand, ns, stream, [&](int v) {
+                        return launch_fused(grp.K, grad, v, cones, 0, ns, P->d_cut, grp.rowcap, ea, stream);
+                    }, variant));
+                }
+            }
+        }
         QCHECK(tm.begin(grp.K, items));
         if (P->opt.one_cone_at_a_time) {
             for (int64_t it = 0; it < items; ++it)
-                QCHECK(launch_fused(grp.K, grad, cones, it, it + 1, P->d_cut, grp.rowcap, ea, stream));
+                QCHECK(launch_fused(grp.K, grad, 0, cones, it, it + 1, P->d_cut, grp.rowcap, ea, stream));
         } else {
-            QCHECK(launch_fused(grp.K, grad, cones, 0, items, P->d_cut, grp.rowcap, ea, stream));
+            QCHECK(launch_fused(grp.K, grad, variant, cones, 0, items, P->d_cut, grp.rowcap, ea, stream));
         }
         QCHECK(tm.end());
     }
@@ -440,6 +539,13 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         // whatever the batching
         int tpw = 1;
         while (tpw < 8 && 2 * tpw <= tiles / 2 && items * tiles / (2 * tpw) >= 4096) tpw *= 2;
+        const TuneKey tkey{arch, 1, k, p, grad ? 1 : 0, 0};
+        bool tune_tpw = false;
+        if (P->opt.tune == 1) {
+            int c = 0;
+            if (tune_lookup(tkey, c)) tpw = c;
+            else tune_tpw = !fixed_batches;
+        }
         // items per batch: within the budget, the grid (a pass launches up to tiles * B
         // workgroups of <= 512 threads: below 2^31 work-items) and no more than needed for
         // 2^17 workgroups (512 per CU) per pass: larger batches hold more memory and gain little
@@ -496,35 +602,53 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
         const std::vector<PassSpec> prog = hbm_program(k, p, grad, ckpt);
         auto slot = [&](int j) { return P->d_phi + ((static_cast<size_t>(std::max(j, 0)) * B) << kh); };
         QCHECK(tm.begin(k, items));
+        auto pass_args = [&](const PassSpec& ps, int64_t i0, int64_t nb) {
+            PassArgs pa{};
+            pa.cones = P->d_hcones + grp.first;
+            pa.e_a = P->d_ea;
+            pa.e_b = P->d_eb;
+            pa.e_w = P->d_ew;
+            pa.tt = P->d_tt;
+            pa.phi_in = slot(ps.ck_in);
+            pa.phi = ps.kind >= RV_GEN_MIX ? slot(ps.ck_in) : slot(ps.ck_out);
+            pa.store_phi = ps.store_phi;
+            pa.lam = P->d_lam;
+            pa.gpart = P->d_gpart;
+            pa.item0 = i0;
+            pa.n_batch = static_cast<int32_t>(nb);
+            pa.k = k;
+            pa.kh = kh;
+            pa.group = ps.group;
+            pa.la = ps.la;
+            pa.lb = ps.lb;
+            pa.m0a = ps.m0a;
+            pa.m0b = ps.m0b;
+            pa.rowcap = grp.rowcap;
+            pa.fix_layer = ps.fix_layer;
+            pa.fix_pow = ps.fix_pow;
+            pa.tpw = tpw;
+            pa.ea = ea;
+            return pa;
+        };
+        if (tune_tpw) {
+            // tiles per workgroup: the class's first pass on its first batch (a generating
+            // pass: it reads no state, and the partial sums it adds are cleared below)
+            std::vector<int> cand;
+            const int64_t units = tiles / 2;   // tile pairs of group 0 (the fewest units)
+            for (int c = 1; c <= 8; c *= 2)
+                if (c <= units && units % c == 0) cand.push_back(c);
+            const int64_t nb = std::min<int64_t>(B, items);
+            QCHECK(tune_pick(tkey, cand, nb, stream, [&](int c) {
+                PassArgs pa = pass_args(prog[0], 0, nb);
+                pa.tpw = c;
+                return launch_pass(prog[0].kind, pa, stream);
+            }, tpw));
+        }
         for (int64_t i0 = 0; i0 < items; i0 += B) {
             const int64_t nb = std::min<int64_t>(B, items - i0);
             QCHECK(launch_fill_zero(P->d_gpart, nb * tiles * stride, stream));
             for (const PassSpec& ps : prog) {
-                PassArgs pa{};
-                pa.cones = P->d_hcones + grp.first;
-                pa.e_a = P->d_ea;
-                pa.e_b = P->d_eb;
-                pa.e_w = P->d_ew;
-                pa.tt = P->d_tt;
-                pa.phi_in = slot(ps.ck_in);
-                pa.phi = ps.kind >= RV_GEN_MIX ? slot(ps.ck_in) : slot(ps.ck_out);
-                pa.store_phi = ps.store_phi;
-                pa.lam = P->d_lam;
-                pa.gpart = P->d_gpart;
-                pa.item0 = i0;
-                pa.n_batch = static_cast<int32_t>(nb);
-                pa.k = k;
-                pa.kh = kh;
-                pa.group = ps.group;
-                pa.la = ps.la;
-                pa.lb = ps.lb;
-                pa.m0a = ps.m0a;
-                pa.m0b = ps.m0b;
-                pa.rowcap = grp.rowcap;
-                pa.fix_layer = ps.fix_layer;
-                pa.fix_pow = ps.fix_pow;
-                pa.tpw = tpw;
-                pa.ea = ea;
+                const PassArgs pa = pass_args(ps, i0, nb);
                 QCHECK(launch_pass(ps.kind, pa, stream));
                 if (!fixed_batches) P->pass_launches[ps.kind] += 1;
             }
@@ -599,6 +723,26 @@ qaoa_status run_energy(qaoa_plan_s* P, int64_t n_points, const double* gamma, co
     if (graph) hipGraphDestroy(graph);
     if (st == QAOA_OK) P->gkey = key;
     return st;
+}
+
+std::string tuning_report() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::string out;
+    char line[256];
+    for (const auto& kv : g_tune) {
+        const TuneKey& key = kv.first;
+        const TuneRec& r = kv.second;
+        std::snprintf(line, sizeof(line), "%s %s k=%d p=%d grad=%d realw=%d items=%lld choice=%d ms:",
+                      key.arch.c_str(), key.what == 0 ? "workgroup-variant" : "passes-tiles-per-workgroup", key.k,
+                      key.p, key.grad, key.realw, static_cast<long long>(r.items), r.choice);
+        out += line;
+        for (const auto& cm : r.ms) {
+            std::snprintf(line, sizeof(line), " %d=%.4f", cm.first, cm.second);
+            out += line;
+        }
+        out += "\n";
+    }
+    return out;
 }
 
 void release_device(qaoa_plan_s* P) {

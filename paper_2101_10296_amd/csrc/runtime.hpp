@@ -96,6 +96,9 @@ qaoa_status run_energy(qaoa_plan_s* plan, int64_t n_points, const double* gamma,
 
 void release_device(qaoa_plan_s* plan);
 
+// The run-time tuner's choices so far (one line per kernel class).
+std::string tuning_report();
+
 // Records msg as this thread's last error (capi.hip) and returns st.
 qaoa_status set_last_error(qaoa_status st, const std::string& msg);
 void clear_last_error();
@@ -103,8 +106,10 @@ qaoa_status kernel_times(qaoa_plan_s* plan, int32_t cap, int32_t* k_out, int64_t
                          int32_t* n_out, std::string& msg);
 
 // kernel launchers
-hipError_t launch_fused(int K, bool grad, const ConeDev* cones, int64_t item_base, int64_t n_items,
+// variant: layout of the workgroup kernel (0 default; see Fz in fused_impl.hpp)
+hipError_t launch_fused(int K, bool grad, int variant, const ConeDev* cones, int64_t item_base, int64_t n_items,
                         const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st);
+std::vector<int> fused_variants(int K, bool grad);
 hipError_t launch_tables(const double* gamma, const double* beta, int64_t n_pl, int32_t R, int32_t cmin,
                          const double* deltas, int64_t pl_per_inst, float2* phase, float2* mix, hipStream_t st);
 hipError_t launch_cut_tables(const ConeDev* cones, int64_t n_cones, const int32_t* ea, const int32_t* eb,
