@@ -313,6 +313,30 @@ def config4_measure(Q, torch, W) -> dict:
                                "achieved_GBps": round(hbm_b / (hbm_ms * 1e-3) / 1e9, 1) if hbm_ms else None}}
 
 
+def tuner_measure(Q, torch, W, gt, bt, graphs, reps: int = 3) -> dict:
+    """The bench workload (both p = 2 graphs, 256 points, energy and gradient) with plans
+    built once: default layouts against plans with the run-time tuner on (its first call
+    times the candidates of every kernel class it meets; the timed calls use the choices)."""
+    out = {}
+    for tune in (False, True):
+        plans = [Q.Plan(g.n, g.edges, p=pp, generators=gens, tune=tune) for g, pp, gens in graphs]
+        for pl in plans:
+            pl.energy_grad(gt, bt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for pl in plans:
+                pl.energy_grad(gt, bt)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["tuned" if tune else "default"] = {"ms_per_step": round(dt * 1e3, 3),
+                                               "evals_per_s": round(len(graphs) * gt.shape[0] / dt, 1)}
+        for pl in plans:
+            pl.close()
+    out["choices"] = [ln for ln in Q.tuning_report().splitlines() if ln]
+    return out
+
+
 def config5i_measure(Q, torch, W) -> dict:
     """Hypercube Q_12 at p = 1: one orbit, one 24-qubit cone; energy and gradient at 8 points
     (the p = 1 pass keeps no state: its roofline is the vector ALU)."""
@@ -621,6 +645,7 @@ def main():
     }
     line.update(extra)
     if not a.no_plain:
+        line["tuner"] = tuner_measure(Q, torch, W, gt, bt, graphs)
         line["config4"] = config4_measure(Q, torch, W)
         line["config5i"] = config5i_measure(Q, torch, W)
     if a.hbm_points > 0:

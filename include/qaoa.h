@@ -45,8 +45,7 @@ enum {
     QAOA_EINVAL = -1,   /* bad sizes or ids, self-loop, duplicate edge, p outside [1, 1024],
                            n_points outside [1, 2^30], non-finite weights */
     QAOA_ENOTAUT = -2,  /* a generator is not a weight-preserving automorphism */
-    QAOA_ECONE = -3,    /* a light cone exceeds max_cone_qubits, or a cone held in device
-                           memory (above 14 qubits) has real weights (see edge_w) */
+    QAOA_ECONE = -3,    /* a light cone exceeds max_cone_qubits */
     QAOA_ENOMEM = -4,   /* not even one work item fits the memory budget / device memory */
     QAOA_EHIP = -5      /* HIP runtime error (no device, launch failure, ...) */
 };
@@ -70,8 +69,8 @@ typedef struct {
                                      relative, at most 2^24 units each) with cut values
                                      spanning at most 255 units per cone use integer cut
                                      tables; any other weights (irrational, Gaussian
-                                     couplings, wide ranges) use real cut values per amplitude,
-                                     for cones of at most 14 qubits (else QAOA_ECONE) */
+                                     couplings, wide ranges) use real cut values per
+                                     amplitude (qaoa_plan_info.real_weights) */
     int32_t n_generators;         /* >= 0 */
     const int32_t* generators;    /* row-major [n_generators][n_nodes]: image of node i under
                                      generator g; NULL / 0 = trivial group */

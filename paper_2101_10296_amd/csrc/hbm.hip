@@ -31,6 +31,32 @@ __global__ void k_tt_tables(const ConeHbm* __restrict__ cones, const int32_t* __
     }
 }
 
+// Real weights: the C_tt table of (cone, group) as floats (FP64 sums rounded once).
+__global__ void k_tt_tables_real(const ConeHbm* __restrict__ cones, const int32_t* __restrict__ ea,
+                                 const int32_t* __restrict__ eb, const double* __restrict__ ew,
+                                 float* __restrict__ tt) {
+    const ConeHbm cd = cones[blockIdx.x];
+    const int grp = blockIdx.y;
+    if (grp >= cd.n_groups) return;
+    __shared__ int32_t pos[32];
+    if (threadIdx.x < 32) pos[threadIdx.x] = -1;
+    __syncthreads();
+    if (threadIdx.x < HT) {
+        int h;
+        pos[hgroup_bits(cd.k - 1, grp, threadIdx.x, h)] = threadIdx.x;
+    }
+    __syncthreads();
+    float* out = tt + cones[blockIdx.x].tt_off[grp];
+    for (uint32_t q = threadIdx.x; q < HN; q += blockDim.x) {
+        double c = 0.0;
+        for (int e = 0; e < cd.n_edges; ++e) {
+            const int pa = pos[ea[cd.edge_off + e]], pb = pos[eb[cd.edge_off + e]];
+            if (pa >= 0 && pb >= 0 && (((q >> pa) ^ (q >> pb)) & 1u)) c += ew[cd.edge_off + e];
+        }
+        out[q] = static_cast<float>(c);
+    }
+}
+
 __global__ void k_fill_zero(double* __restrict__ x, int64_t n) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -75,6 +101,11 @@ static hipError_t launch_one(const PassArgs& pa, hipStream_t st) {
     const int64_t units = CF >= 2 ? tiles / 2 : tiles;   // tile pairs on group 0
     if (pa.tpw < 1 || units % pa.tpw != 0) return hipErrorInvalidValue;
     const int64_t blocks = units * pa.n_batch / pa.tpw;
+    if (pa.ea.realw) {   // real weights: per-amplitude phases, no rows, one LDS buffer
+        hipLaunchKernelGGL((k_pass<KIND, G0, false, true>), dim3(static_cast<unsigned>(blocks)), dim3(Hz<CF>::W), 0,
+                           st, pa);
+        return hipGetLastError();
+    }
     const size_t dyn = 3 * static_cast<size_t>(pa.rowcap) * sizeof(float2);   // three phase rows
     if constexpr (CF == 3) {
         // two LDS buffers when they fit beside the phase rows
@@ -118,6 +149,14 @@ hipError_t launch_tt_tables(const ConeHbm* cones, int64_t n_cones, int max_group
                             const int32_t* eb, const int32_t* ew, uint8_t* tt, hipStream_t st) {
     if (n_cones <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tt_tables, dim3(static_cast<unsigned>(n_cones), static_cast<unsigned>(max_groups)),
+                       dim3(256), 0, st, cones, ea, eb, ew, tt);
+    return hipGetLastError();
+}
+
+hipError_t launch_tt_tables_real(const ConeHbm* cones, int64_t n_cones, int max_groups, const int32_t* ea,
+                                 const int32_t* eb, const double* ew, float* tt, hipStream_t st) {
+    if (n_cones <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tt_tables_real, dim3(static_cast<unsigned>(n_cones), static_cast<unsigned>(max_groups)),
                        dim3(256), 0, st, cones, ea, eb, ew, tt);
     return hipGetLastError();
 }

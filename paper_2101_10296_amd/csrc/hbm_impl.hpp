@@ -69,7 +69,7 @@ struct ConeHbm {
     int64_t tt_off[4];   // byte offset of the C_tt table of each group
     int32_t tt_min[4];   // value subtracted before storing C_tt as a byte
     int32_t inst;        // instance of the cone (angle tables per instance)
-    int32_t pad_;
+    float c0;            // real weights: centre of the cone's cut range (subtracted from C)
 };
 
 struct PassArgs {
@@ -77,7 +77,8 @@ struct PassArgs {
     const int32_t* e_a;        // flattened cone edges (qubit pairs) and weights
     const int32_t* e_b;
     const int32_t* e_w;
-    const uint8_t* tt;         // C_tt tables
+    const double* e_wd;        // real weights of the cone edges (plans with real weights)
+    const uint8_t* tt;         // C_tt tables (real weights: floats, tt_off counting floats)
     const float2* phi_in;      // state the pass reads [batch][2^kh] (forward input; for a reverse
                                // pass the state at the output of the forward pass it undoes)
     float2* phi;               // state the pass writes [batch][2^kh] (may equal phi_in)
@@ -419,9 +420,47 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
     return s;
 }
 
+// Real weights: the cut value of every amplitude as a float, C - c0 = (k0 - c0) +
+// sum_b q_b L_b + C_tt(q) with the coefficients summed in FP64 by one thread each (a fixed
+// order), and its phase computed per amplitude (rphase).  cv(r) gives register r's value in
+// layout 0.
+template <int A, class CV>
+__device__ __forceinline__ void gen_stage_cv(float2 (&f)[A], CV&& cv, double gpi, float sc) {
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 t = rphase(gpi, cv(r));
+        f[r] = make_float2(sc * t.x, sc * t.y);
+    }
+}
+template <int A, class CV>
+__device__ __forceinline__ void phase_stage_cv(float2 (&f)[A], CV&& cv, double gpi, float sc) {
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 t = rphase(gpi, cv(r));
+        f[r] = cmul(f[r], make_float2(sc * t.x, sc * t.y));
+    }
+}
+template <bool UNDO, int A, class CV>
+__device__ __forceinline__ float cgrad_stage_cv(float2 (&f)[A], float2 (&l)[A], CV&& cv, double gpi, float c0,
+                                                float sc) {
+    float a = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float c = cv(r);
+        cacc(a, c + c0, l[r], f[r]);
+        if constexpr (UNDO) {
+            const float2 t0 = rphase(gpi, c);
+            const float2 t = make_float2(sc * t0.x, sc * t0.y);
+            f[r] = cmulc(f[r], t);
+            l[r] = cmulc(l[r], t);
+        }
+    }
+    return a;
+}
+
 // DB: two LDS buffers (psi and lambda transposed together) for the adjoint tile-pair
-// passes, which run one workgroup per CU anyway (registers).
-template <int KIND, bool G0, bool DB = false>
+// passes, which run one workgroup per CU anyway (registers).  RW: real weights (one buffer).
+template <int KIND, bool G0, bool DB = false, bool RW = false>
 __global__ void __launch_bounds__((Hz<pass_cf(KIND, G0)>::W), (Hz<pass_cf(KIND, G0)>::WPE))
 k_pass(PassArgs pa) {
     constexpr int CF = pass_cf(KIND, G0);
@@ -436,8 +475,9 @@ k_pass(PassArgs pa) {
                             KIND == GR_BND_FINAL);
     constexpr bool CUTS = !(KIND == FWD_MIX || KIND == RV_MIX);   // phases or C inner products
     __shared__ float2 xbuf[(DB ? 2 : 1) * H::NPAD];
-    __shared__ __attribute__((aligned(16))) uint8_t ttl[HN];
+    __shared__ __attribute__((aligned(16))) uint8_t ttl[RW ? 4 * HN : HN];   // C_tt: bytes, or floats (RW)
     __shared__ int32_t lcoef[NT][HT];
+    __shared__ float lcf[RW ? NT : 1][HT + 1];   // RW: L_b and k0 - c0 of the unit's tiles
     __shared__ double red[H::W / 64];
     __shared__ int32_t k0_sh[NT];
     __shared__ int8_t tpos[32];          // tile bit of each global bit, -1 outside the tile
@@ -470,7 +510,11 @@ k_pass(PassArgs pa) {
     const float2* row_first = rows;
     const float2* row_lb = rows + pa.rowcap;
     const float2* row_last = rows + 2 * pa.rowcap;
-    if constexpr (CUTS) {
+    if constexpr (CUTS && RW) {
+        const float* src = reinterpret_cast<const float*>(pa.tt) + pa.cones[cslot].tt_off[pa.group];
+        for (uint32_t q = tau * 4; q < HN; q += H::W * 4)
+            *reinterpret_cast<float4*>(reinterpret_cast<float*>(ttl) + q) = *reinterpret_cast<const float4*>(src + q);
+    } else if constexpr (CUTS) {
         const uint8_t* src = pa.tt + pa.cones[cslot].tt_off[pa.group];
         for (uint32_t q = tau * 16; q < HN; q += H::W * 16)
             *reinterpret_cast<uint4*>(ttl + q) = *reinterpret_cast<const uint4*>(src + q);
@@ -586,7 +630,50 @@ k_pass(PassArgs pa) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) xo[t] = outer_of(t ? tiles - 1 - unit : unit);
         uint32_t pk[NT][NW];
-        if constexpr (CUTS) {
+        // real weights: the thread's base value, the register-bit coefficients and the
+        // thread bits of each tile in layout 0
+        float lthrf[NT], lcr[NT][H::AB];
+        uint32_t qbt[NT];
+        const float* ttf = reinterpret_cast<const float*>(ttl);
+        if constexpr (CUTS && RW) {
+            __syncthreads();   // the previous unit has read lcf
+            if (tid < NT * (HT + 1)) {
+                // coefficient b of tile t (b = HT: the constant, minus c0), summed in FP64 over
+                // the cone's edges in their order
+                const int t = tid / (HT + 1), b = tid - t * (HT + 1);
+                const uint64_t x = xo[t];
+                double acc = 0.0;
+                for (int e = 0; e < cd.n_edges; ++e) {
+                    const int ea_ = pa.e_a[cd.edge_off + e], eb_ = pa.e_b[cd.edge_off + e];
+                    const double w = pa.e_wd[cd.edge_off + e];
+                    const int ia = tpos[ea_], ib = tpos[eb_];
+                    const int xa = static_cast<int>((x >> ea_) & 1u), xb = static_cast<int>((x >> eb_) & 1u);
+                    if (b < HT) {
+                        if (ia == b && ib < 0) acc += xb ? -w : w;
+                        else if (ib == b && ia < 0) acc += xa ? -w : w;
+                    } else if (ia >= 0 && ib < 0) {
+                        if (xb) acc += w;
+                    } else if (ia < 0 && ib >= 0) {
+                        if (xa) acc += w;
+                    } else if (ia < 0 && ib < 0 && (xa ^ xb)) {
+                        acc += w;
+                    }
+                }
+                lcf[t][b] = b < HT ? static_cast<float>(acc) : static_cast<float>(acc - static_cast<double>(cd.c0));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                qbt[t] = t ? (~htbase<CF, 0>(tau) & TBITS_0) : htbase<CF, 0>(tau);
+                float c = lcf[t][HT];
+#pragma unroll
+                for (int i = H::AB; i < HT; ++i)
+                    if ((qbt[t] >> i) & 1u) c += lcf[t][i];
+                lthrf[t] = c;
+#pragma unroll
+                for (int i = 0; i < H::AB; ++i) lcr[t][i] = lcf[t][i];
+            }
+        } else if constexpr (CUTS) {
             __syncthreads();   // the previous unit has read lcoef and k0
             if (tid < HT) {
 #pragma unroll
@@ -639,6 +726,21 @@ k_pass(PassArgs pa) {
                 }
             }
         }
+        // register r of tile t (layout 0): its real cut value minus c0
+        auto CV = [&](int t) {
+            return [&, t](int r) {
+                const int rr = t ? A - 1 - r : r;
+                float c = lthrf[t] + ttf[qbt[t] | hroff<CF, 0>(rr)];
+#pragma unroll
+                for (int i = 0; i < H::AB; ++i)
+                    if ((rr >> i) & 1) c += lcr[t][i];
+                return c;
+            };
+        };
+        const double* gam = RW ? pa.ea.gamma + (static_cast<size_t>(cd.inst) * pa.ea.gamma_P + point) * p : nullptr;
+        auto GPI = [&](int l) { return gam[l] * 0.31830988618379067154; };   // gamma_(l+1) / pi
+        (void)CV;
+        (void)GPI;
         size_t off[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) off[t] = (static_cast<size_t>(bslot) << kh) + xo[t];
@@ -647,7 +749,10 @@ k_pass(PassArgs pa) {
         // ------------------------------------------------------------ forward part
         if constexpr (KIND == FWD_GEN_MIX || KIND == FWD_GEN_FINAL || KIND == GR_GEN_FINAL) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) gen_stage(f[t], pk[t], row_first, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
+            for (int t = 0; t < NT; ++t) {
+                if constexpr (RW) gen_stage_cv(f[t], CV(t), GPI(0), exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
+                else gen_stage(f[t], pk[t], row_first, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
+            }
             if constexpr (KIND == FWD_GEN_MIX) {
                 const float t1 = mix0[0].x;
 #pragma unroll
@@ -677,8 +782,10 @@ k_pass(PassArgs pa) {
                 continue;
             }
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-                phase_stage(f[t], pk[t], row_lb, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
+            for (int t = 0; t < NT; ++t) {
+                if constexpr (RW) phase_stage_cv(f[t], CV(t), GPI(pa.lb - 1), kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
+                else phase_stage(f[t], pk[t], row_lb, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
+            }
             if constexpr (KIND == FWD_BND_MIX) {
                 const float tb = mix0[pa.lb - 1].x;
 #pragma unroll
@@ -737,13 +844,18 @@ k_pass(PassArgs pa) {
                 if constexpr (KIND == GR_GEN_FINAL) {
                     float a = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
+                    for (int t = 0; t < NT; ++t) {
+                        if constexpr (RW) a += cgrad_stage_cv<false>(f[t], lm[t], CV(t), 0.0, cd.c0, 1.f);
+                        else a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
+                    }
                     part[2] += 2.0 * static_cast<double>(mu) * mu * a;
                 } else {
                     float a = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        a += cgrad_stage<true>(f[t], lm[t], pk[t], row_last, cd.cut_min, mu);
+                    for (int t = 0; t < NT; ++t) {
+                        if constexpr (RW) a += cgrad_stage_cv<true>(f[t], lm[t], CV(t), GPI(p - 1), cd.c0, mu);
+                        else a += cgrad_stage<true>(f[t], lm[t], pk[t], row_last, cd.cut_min, mu);
+                    }
                     part[2] += 2.0 * static_cast<double>(mu) * mu * a;
                     // mixer la = p-1 on this group: psi is not needed after this pass (the next
                     // reverse pass reads it from device memory), so the inner products of all
@@ -840,13 +952,18 @@ k_pass(PassArgs pa) {
                 if constexpr (KIND == RV_GEN_MIX) {
                     float a = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
+                    for (int t = 0; t < NT; ++t) {
+                        if constexpr (RW) a += cgrad_stage_cv<false>(f[t], lm[t], CV(t), 0.0, cd.c0, 1.f);
+                        else a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
+                    }
                     part[1] += 2.0 * static_cast<double>(mu) * mu * a;
                 } else {
                     float a = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        a += cgrad_stage<true>(f[t], lm[t], pk[t], row_lb, cd.cut_min, mu);
+                    for (int t = 0; t < NT; ++t) {
+                        if constexpr (RW) a += cgrad_stage_cv<true>(f[t], lm[t], CV(t), GPI(pa.lb - 1), cd.c0, mu);
+                        else a += cgrad_stage<true>(f[t], lm[t], pk[t], row_lb, cd.cut_min, mu);
+                    }
                     part[1] += 2.0 * static_cast<double>(mu) * mu * a;
                     const float2 tka = mix0[pa.la - 1];
                     const float wa0 = exp2f(pa.m0a * log2f(tka.y));

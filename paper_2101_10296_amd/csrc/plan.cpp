@@ -351,12 +351,6 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
     P.cut_max = 0;
     if (P.realw) {
         P.delta = 1.0;
-        for (int64_t o = 0; o < M; ++o)
-            if (P.cones[o].k > opt.k_lds_max)
-                fail(kECONE, "light cone of orbit " + std::to_string(o) + " has " + std::to_string(P.cones[o].k) +
-                                 " qubits: cones held in device memory need weights with a common unit whose cut "
-                                 "values span at most 255 units (real weights are evaluated for cones of at most " +
-                                 std::to_string(opt.k_lds_max) + " qubits)");
     } else {
         for (const Cone& c : P.cones) {
             P.cut_min = std::min<int32_t>(P.cut_min, c.cut_min);
@@ -426,10 +420,6 @@ void merge_host_plans(std::vector<HostPlan>& parts, HostPlan& P) {
         P.delta = 1.0;
         P.cut_min = P.cut_max = 0;
         std::fill(P.inst_delta.begin(), P.inst_delta.end(), 1.0);
-        for (size_t o = 0; o < P.cones.size(); ++o)
-            if (P.cones[o].k > 14)
-                fail(kECONE, "light cone of orbit " + std::to_string(o) + " has " + std::to_string(P.cones[o].k) +
-                                 " qubits: with real weights in a batch, every cone must have at most 14 qubits");
     }
 }
 

@@ -35,7 +35,7 @@ struct HostPlan {
     bool unit = true;
     // real weights: no common unit (or a cone's cut values span more than 255 units): cut
     // values are real numbers, the phase of every amplitude is computed from its own cut
-    // value (workgroup-resident cones only); delta = 1 and wi are unused
+    // value; delta = 1 and wi are unused
     bool realw = false;
     std::vector<int32_t> edge_orbit;       // [m]
     std::vector<int64_t> rep, size;        // [M]

@@ -312,6 +312,7 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         d.cut_range = c.cut_max - c.cut_min + 1;
         d.cut_shift = c.cut_min - hp.cut_min;
         d.inst = c.inst;
+        d.c0 = static_cast<float>(0.5 * (c.cf_min + c.cf_max));
         d.n_groups = hbm_groups_of(c.k - 1);
         max_groups = std::max(max_groups, d.n_groups);
         for (int g = 0; g < d.n_groups; ++g) {
@@ -322,12 +323,14 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
             for (size_t e = 0; e < c.ea.size(); ++e)
                 if (in[c.ea[e]] && in[c.eb[e]]) (c.ew[e] < 0 ? tmin : tmax) += c.ew[e];
             d.tt_min[g] = tmin;
-            d.tt_off[g] = tt_bytes;
-            tt_bytes += 8192;
+            // byte table of 2^13 entries, or (real weights) floats: tt_off then counts floats
+            d.tt_off[g] = hp.realw ? tt_bytes / 4 : tt_bytes;
+            tt_bytes += hp.realw ? 4 * 8192 : 8192;
         }
         ea.insert(ea.end(), c.ea.begin(), c.ea.end());
         eb.insert(eb.end(), c.eb.begin(), c.eb.end());
         ew.insert(ew.end(), c.ew.begin(), c.ew.end());
+        if (hp.realw) ewd.insert(ewd.end(), c.wf.begin(), c.wf.end());
         if (P->hbm_groups.empty() || P->hbm_groups.back().K != c.k)
             P->hbm_groups.push_back({c.k, static_cast<int64_t>(s), 0, 1});
         P->hbm_groups.back().count += 1;
@@ -367,25 +370,24 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         QCHECK(hipMemcpy(P->d_ew, ew.data(), ew.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     if (hp.realw) {
-        double* d_ewd = nullptr;
-        QCHECK(hipMalloc(&d_ewd, std::max<size_t>(ewd.size(), 1) * sizeof(double)));
-        hipError_t e1 = ewd.empty() ? hipSuccess
-                                    : hipMemcpy(d_ewd, ewd.data(), ewd.size() * sizeof(double), hipMemcpyHostToDevice);
-        if (e1 == hipSuccess)
-            e1 = launch_cut_tables_real(P->d_cones, M, P->d_ea, P->d_eb, d_ewd, reinterpret_cast<float*>(P->d_cut),
-                                        nullptr);
-        if (e1 == hipSuccess) e1 = hipDeviceSynchronize();
-        hipFree(d_ewd);
-        QCHECK(e1);
+        // real weights stay resident: the device-memory passes sum each tile's coefficients
+        QCHECK(hipMalloc(&P->d_ewd, std::max<size_t>(ewd.size(), 1) * sizeof(double)));
+        if (!ewd.empty())
+            QCHECK(hipMemcpy(P->d_ewd, ewd.data(), ewd.size() * sizeof(double), hipMemcpyHostToDevice));
+        QCHECK(launch_cut_tables_real(P->d_cones, M, P->d_ea, P->d_eb, P->d_ewd, reinterpret_cast<float*>(P->d_cut),
+                                      nullptr));
+        QCHECK(launch_tt_tables_real(P->d_hcones, static_cast<int64_t>(hc.size()), max_groups, P->d_ea, P->d_eb,
+                                     P->d_ewd, reinterpret_cast<float*>(P->d_tt), nullptr));
     } else {
         QCHECK(launch_cut_tables(P->d_cones, M, P->d_ea, P->d_eb, P->d_ew, P->d_cut, nullptr));
+        QCHECK(launch_tt_tables(P->d_hcones, static_cast<int64_t>(hc.size()), max_groups, P->d_ea, P->d_eb,
+                                P->d_ew, P->d_tt, nullptr));
     }
-    QCHECK(launch_tt_tables(P->d_hcones, static_cast<int64_t>(hc.size()), max_groups, P->d_ea, P->d_eb, P->d_ew,
-                            P->d_tt, nullptr));
     QCHECK(hipDeviceSynchronize());
     P->resident_bytes = cd.size() * sizeof(ConeDev) + static_cast<size_t>(cut_bytes) + hp.W.size() * sizeof(double) +
                         hc.size() * sizeof(ConeHbm) + static_cast<size_t>(tt_bytes) + 3 * ne * sizeof(int32_t) +
-                        hp.inst_orbit.size() * sizeof(int64_t) + 2 * hp.inst_delta.size() * sizeof(double);
+                        hp.inst_orbit.size() * sizeof(int64_t) + 2 * hp.inst_delta.size() * sizeof(double) +
+                        ewd.size() * sizeof(double);
     P->device = dev;
     P->dev_ready = true;
     return QAOA_OK;
@@ -608,6 +610,7 @@ qaoa_status enqueue(qaoa_plan_s* P, int64_t n_points, const double* gamma, const
             pa.e_a = P->d_ea;
             pa.e_b = P->d_eb;
             pa.e_w = P->d_ew;
+            pa.e_wd = P->d_ewd;
             pa.tt = P->d_tt;
             pa.phi_in = slot(ps.ck_in);
             pa.phi = ps.kind >= RV_GEN_MIX ? slot(ps.ck_in) : slot(ps.ck_out);
@@ -773,6 +776,8 @@ void release_device(qaoa_plan_s* P) {
     hipFree(P->d_phi);
     hipFree(P->d_lam);
     hipFree(P->d_gpart);
+    hipFree(P->d_ewd);
+    P->d_ewd = nullptr;
     hipFree(P->d_inst_orbit);
     hipFree(P->d_inst_delta);
     hipFree(P->d_ones);

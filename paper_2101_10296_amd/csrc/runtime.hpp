@@ -37,6 +37,7 @@ struct qaoa_plan_s {
     std::vector<HGroup> hbm_groups;
     qaoa::ConeHbm* d_hcones = nullptr;
     int32_t *d_ea = nullptr, *d_eb = nullptr, *d_ew = nullptr;
+    double* d_ewd = nullptr;            // real weights of the cone edges (real-weight plans)
     uint8_t* d_tt = nullptr;
     double* d_W = nullptr;
     int64_t* d_inst_orbit = nullptr;    // [n_inst + 1]
@@ -119,6 +120,8 @@ hipError_t launch_cut_tables_real(const ConeDev* cones, int64_t n_cones, const i
 hipError_t launch_pass(int kind, const PassArgs& pa, hipStream_t st);
 hipError_t launch_tt_tables(const ConeHbm* cones, int64_t n_cones, int max_groups, const int32_t* ea,
                             const int32_t* eb, const int32_t* ew, uint8_t* tt, hipStream_t st);
+hipError_t launch_tt_tables_real(const ConeHbm* cones, int64_t n_cones, int max_groups, const int32_t* ea,
+                                 const int32_t* eb, const double* ew, float* tt, hipStream_t st);
 hipError_t launch_fill_zero(double* x, int64_t n, hipStream_t st);
 hipError_t launch_tile_reduce(const ConeHbm* cones, const double* gpart, int64_t item0, int64_t n_batch,
                               int64_t tiles, int32_t stride, int32_t nvals, const EvalArgs& ea, hipStream_t st);

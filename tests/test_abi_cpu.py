@@ -151,10 +151,9 @@ def test_real_weights():
     pl = Q.Plan(c.n, c.edges, p=2, weights=w, generators=c.gens())
     assert pl.info()["real_weights"] == 1 and pl.info()["n_orbits"] == 2
     assert Q.Plan(c.n, c.edges, p=2, weights=np.where(w == 1.0, 1.0, 2.0)).info()["real_weights"] == 0
-    s = W.star(15)   # one 16-qubit cone: held in device memory, which needs integer cut values
-    with pytest.raises(Q.QaoaError) as ei:
-        Q.Plan(s.n, s.edges, p=1, weights=np.full(s.m, 30.0))
-    assert ei.value.status == Q.QAOA_ECONE and "orbit 0 has 16 qubits" in str(ei.value)
+    s = W.star(15)   # one 16-qubit cone, held in device memory: real weights there too
+    info = Q.Plan(s.n, s.edges, p=1, weights=np.full(s.m, 30.0)).info()
+    assert info["real_weights"] == 1 and info["n_hbm_cones"] == s.m
 
 
 def test_empty_and_isolated():
@@ -176,15 +175,10 @@ def test_first_failing_cone_is_reported():
     assert ei.value.status == Q.QAOA_ECONE
     assert f"light cone of orbit {first} " in str(ei.value)
     # weight 300 on one late edge makes the weights real (its cones' cut values span more
-    # than 255): at p = 3 the lowest orbit whose cone is held in device memory is named
+    # than 255 units); that is no error any more
     w = np.ones(g.m)
     w[g.m - 5] = 300.0
-    with pytest.raises(Q.QaoaError) as ei:
-        Q.Plan(g.n, g.edges, p=3, weights=w)
-    assert ei.value.status == Q.QAOA_ECONE
-    cones = oracle.plan(g.n, g.edges, None, None, 3, reduce=True, max_k=40)["cones"]
-    first = next(m for m, c in enumerate(cones) if c["k"] > 14)
-    assert f"light cone of orbit {first} has " in str(ei.value)
+    assert Q.Plan(g.n, g.edges, p=1, weights=w).info()["real_weights"] == 1
 
 
 def test_batch_plan_concatenates_instances():

@@ -205,3 +205,28 @@ def test_deep_weighted_star_rows_in_device_memory(Q):
     w = np.full(g.m, 17.0)
     ga, be = W.draw_angles(2, 45, 93)
     check_energy(Q, g, 45, ga, be, weights=w)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_real_weights_device_memory_star(Q, p):
+    # the 16-qubit star (two tile pairs) with Gaussian couplings: real cut values in the
+    # device-memory passes, every depth's pass kinds
+    g = W.star(15)
+    w = np.random.default_rng(20 + p).normal(size=g.m)
+    ga, be = W.draw_angles(3, p, 75 + p)
+    pl, _, _ = check_energy(Q, g, p, ga, be, reduce=False, weights=w, grad=True)
+    assert pl.info()["real_weights"] == 1 and pl.info()["n_hbm_cones"] == g.m
+
+
+@pytest.mark.parametrize("ckpt", [0, 1])
+def test_real_weights_device_memory_circulant(Q, ckpt):
+    # C_60(1,2,3) with weights 1, sqrt 2, sqrt 3 by step (the rotation and reflection keep
+    # them: three orbits) at p = 3: 20-22-qubit cones in two pass groups, both adjoint modes
+    g = W.circulant(60, (1, 2, 3))
+    d = (g.edges[:, 1] - g.edges[:, 0]) % g.n
+    step = np.minimum(d, g.n - d)
+    w = np.sqrt(step.astype(float))
+    ga, be = W.draw_angles(1, 3, 79)
+    pl, _, _ = check_energy(Q, g, 3, ga, be, reduce=True, weights=w, grad=True,
+                            plan_kw=dict(checkpoint_mode=ckpt))
+    assert pl.info()["real_weights"] == 1 and pl.info()["n_orbits"] == 3
