@@ -208,6 +208,62 @@ __device__ __forceinline__ float unmix_stage2(float2 (&f)[A], float2 (&l)[A], fl
     return acc;
 }
 
+// Last stage of the undo of layer 1: psi is not needed after it (D_1 |+> is regenerated
+// from the cut table), so every term of the stage is taken at its entry (X_j commutes with
+// all rotations of its layer, so the entry point is as good as the point after X_j's own
+// undo) with the entry weight w, and the mixer is undone on lambda alone.
+template <int K, int G, int ST, int A>
+__device__ __forceinline__ float unmix_stage_last(const float2 (&f)[A], float2 (&l)[A], float t, float w) {
+    constexpr int AB = Fz<K, G>::AB;
+    constexpr bool LANE = Fz<K, G>::LQ && ST == Fz<K, G>::S - 1;
+    float a0 = 0.f, a1 = 0.f;
+    if constexpr (LANE) {
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            if (r & 1) cacc(a1, 1.f, l[r], lane_x1(f[r]));
+            else cacc(a0, 1.f, l[r], lane_x1(f[r]));
+            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < AB; ++i) {
+        if (ST * AB + i >= K) continue;
+        int np = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                const int r2 = r | (1 << i);
+                if (np++ & 1) xacc(a1, l[r], l[r2], f[r], f[r2]);
+                else xacc(a0, l[r], l[r2], f[r], f[r2]);
+                if ((np & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (LANE) {
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 lq = lane_x1(l[r]);
+            l[r] = make_float2(fmaf(-t, lq.y, l[r].x), fmaf(t, lq.x, l[r].y));
+            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < AB; ++i) {
+        if (ST * AB + i >= K) continue;
+        int nb = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                bfly(l[r], l[r | (1 << i)], -t);
+                if ((++nb & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return w * (a0 + a1);
+}
+
 // The transpose bases are loop-invariant; an empty asm makes them opaque so that the
 // compiler keeps one base register plus immediate offsets instead of hoisting one
 // address register per amplitude out of the layer loops.
@@ -429,6 +485,25 @@ __device__ __forceinline__ float cgrad_stage(float2 (&f)[A], float2 (&l)[A], uin
     return a;
 }
 
+// D^dagger scaled by sc on lambda alone, then lambda's share of Im <lambda| C |psi> against
+// psi before D (kept from the forward pass): the same term as cgrad_stage takes before its
+// undo, since D is diagonal and unimodular.
+template <int A>
+__device__ __forceinline__ float cterm_lam(float2 (&l)[A], const float2 (&f)[A], uint32_t (&pk)[(A + 3) / 4],
+                                           const float2* row, int cmin, float sc) {
+    opaque<A>(pk);
+    float a = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const int cq = static_cast<int>(cutv<A>(pk, r));
+        const float2 t0 = row[cq];
+        l[r] = cmulc(l[r], make_float2(sc * t0.x, sc * t0.y));
+        cacc(a, static_cast<float>(cq + cmin), l[r], f[r]);
+        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    return a;
+}
+
 // Real weights (no common unit, or cut values spanning more than 255 units): the phase of
 // every amplitude comes from its own cut value, exp(-i gamma C(x)).  The table holds
 // C(x) - c0 (c0 the centre of the cone's cut range: a global phase per layer, which no
@@ -478,6 +553,19 @@ __device__ __forceinline__ float cgrad_stage_rw(float2 (&f)[A], float2 (&l)[A], 
     return a;
 }
 
+template <int A>
+__device__ __forceinline__ float cterm_lam_rw(float2 (&l)[A], const float2 (&f)[A], const float (&cf)[A], double gpi,
+                                              float c0, float sc) {
+    float a = 0.f;
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 t0 = rphase(gpi, cf[r]);
+        l[r] = cmulc(l[r], make_float2(sc * t0.x, sc * t0.y));
+        cacc(a, cf[r] + c0, l[r], f[r]);
+    }
+    return a;
+}
+
 template <int K, int G, int ST, int A>
 __device__ __forceinline__ void load_cuts_rw(float (&cf)[A], const float* cut, uint32_t tau) {
     const float* cb = cut + tbase<K, G, ST>(tau);
@@ -516,7 +604,8 @@ __device__ __forceinline__ void fwd_layer(float2 (&f)[A], float2* xb, uint32_t t
 
 // Undo a forward layer of direction DESC on psi and lambda (stages in reverse order);
 // returns the thread's share of Im <lambda| sum_j X_j |psi>.
-template <int K, int G, bool DESC, bool FLIP, bool DB, int A>
+// LAST: the undo of layer 1, whose last stage leaves psi alone (unmix_stage_last).
+template <int K, int G, bool DESC, bool FLIP, bool DB, bool LAST = false, int A>
 __device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2* xb, float2* xb2, uint32_t tau,
                                           float t, float k2) {
     constexpr int S = Fz<K, G>::S;
@@ -542,7 +631,8 @@ __device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2
                 xpose<K, G, prev, st>(l, xb, tau);
             }
         }
-        acc += static_cast<double>(unmix_stage2<K, G, st>(f, l, t, k2, w));
+        if constexpr (LAST && j == S - 1) acc += static_cast<double>(unmix_stage_last<K, G, st>(f, l, t, w));
+        else acc += static_cast<double>(unmix_stage2<K, G, st>(f, l, t, k2, w));
     });
     return acc;
 }
@@ -662,6 +752,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     const float k2p = mix0[p - 1].y;
 
     float2 f[A];
+    // GRAD: psi after the mixer of layer p-1 at its true norm, kept for the adjoint (which
+    // then undoes D_p and the last mixer on lambda alone)
+    float2 f1[GRAD ? A : 1];
     // ---- D_1 |+>, then the full layers 1..p-1, each followed by the next phase.
     // Phase row l (0-based) is scaled by the norm lost in the layer before it, and the
     // last one also by |kappa_p|^2, so psi leaves the final mixer normalised.
@@ -671,12 +764,25 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         else if constexpr (ODD) gen_stage(f, pkL, ROW(0), sc);
         else gen_stage(f, pk0, ROW(0), sc);
     }
+    // the phase after a descending layer l (stage 0); kk = |kappa_l|^K
+    auto phase_desc = [&](int l, float kk) {
+        if (GRAD && l + 1 == p) {
+#pragma unroll
+            for (int r = 0; r < A; ++r) {
+                f[r] = make_float2(kk * f[r].x, kk * f[r].y);
+                if constexpr (GRAD) f1[r] = f[r];
+            }
+            kk = 1.f;
+        }
+        const float sc = kk * (l + 1 == p ? k2p : 1.f);
+        if constexpr (RW) phase_stage_rw(f, cf0, GPI(l), sc);
+        else phase_stage(f, pk0, ROW(l), sc);
+    };
     int l1 = 1;
     if constexpr (ODD) {
         const float2 tk = mix0[0];
         fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tk.x);
-        if constexpr (RW) phase_stage_rw(f, cf0, GPI(1), kpowK(tk.y) * (p == 2 ? k2p : 1.f));
-        else phase_stage(f, pk0, ROW(1), kpowK(tk.y) * (p == 2 ? k2p : 1.f));
+        phase_desc(1, kpowK(tk.y));
         l1 = 2;
     }
     for (; l1 + 1 <= p - 1; l1 += 2) {
@@ -686,8 +792,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         else phase_stage(f, pkL, ROW(l1), kpowK(ta.y));
         const float2 tb = mix0[l1];
         fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tb.x);
-        if constexpr (RW) phase_stage_rw(f, cf0, GPI(l1 + 1), kpowK(tb.y) * (l1 + 2 == p ? k2p : 1.f));
-        else phase_stage(f, pk0, ROW(l1 + 1), kpowK(tb.y) * (l1 + 2 == p ? k2p : 1.f));
+        phase_desc(l1 + 1, kpowK(tb.y));
     }
 
     // ---- last layer: mixer on qubits 0, 1 (register bits 0, 1 of stage 0); <Z0 Z1>
@@ -723,36 +828,77 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             if (!(r & 2)) xacc(acc, lam[r], lam[r | 2], f[r], f[r | 2]);
         const double gbp = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(acc), red, tid);
         if (valid && tau == 0) gout[static_cast<size_t>(2 * p - 1) * M] = gbp;
-        // undo the last mixer: both states end up scaled by 1/|kappa_p|^2
+        const float mup = k2p;   // the undone last mixer leaves lambda scaled by 1/|kappa_p|^2
+        if (p == 1) {
+            // undo the last mixer on both states; the gamma_1 term (both carry 1/mu_p)
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 2)) { bfly(f[r], f[r | 2], -tp); bfly(lam[r], lam[r | 2], -tp); }
+#pragma unroll
+            for (int r = 0; r < A; ++r)
+                if (!(r & 1)) { bfly(f[r], f[r | 1], -tp); bfly(lam[r], lam[r | 1], -tp); }
+            float a;
+            if constexpr (RW) a = cgrad_stage_rw<false>(f, lam, cf0, 0.0, cd.c0, 1.f);
+            else a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
+            const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mup) * mup * a, red, tid);
+            if (valid && tau == 0) gout[0] = gc;
+            return;
+        }
+        // undo the last mixer on lambda; then D_p on lambda (the row scaled by mu_p restores
+        // its true norm) with the gamma_p term against the kept psi
 #pragma unroll
         for (int r = 0; r < A; ++r)
-            if (!(r & 2)) { bfly(f[r], f[r | 2], -tp); bfly(lam[r], lam[r | 2], -tp); }
+            if (!(r & 2)) bfly(lam[r], lam[r | 2], -tp);
 #pragma unroll
         for (int r = 0; r < A; ++r)
-            if (!(r & 1)) { bfly(f[r], f[r | 1], -tp); bfly(lam[r], lam[r | 1], -tp); }
+            if (!(r & 1)) bfly(lam[r], lam[r | 1], -tp);
+        {
+            float a;
+            if constexpr (RW) a = cterm_lam_rw(lam, f1, cf0, GPI(p - 1), cd.c0, mup);
+            else a = cterm_lam(lam, f1, pk0, ROW(p - 1), cd.cut_min, mup);
+            const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(a), red, tid);
+            if (valid && tau == 0) gout[static_cast<size_t>(p - 1) * M] = gc;
+        }
+#pragma unroll
+        for (int r = 0; r < A; ++r) f[r] = f1[r];
 
-        // Walk the layers back.  Before the gamma_ly term both states carry the factor
-        // 1/mu_ly (mu_p = |kappa_p|^2, mu_ly = |kappa_ly|^K); D_ly is undone with a row
-        // scaled by mu_ly, which restores the true states.  Layer p-1 is descending, so
-        // undoing it ends in stage SL; the layers then alternate.
-        float mu = k2p;
+        // The undo of layer 1 (descending iff ODD) leaves psi alone in its last stage and
+        // regenerates D_1 |+> in the stage it ends in for the gamma_1 term (lambda carries
+        // 1/mu_1, mu_1 = |kappa_1|^K; psi is exact).
+        auto last_layer = [&](auto dir) {
+            constexpr bool D = decltype(dir)::value;
+            const float2 tk = mix0[0];
+            const double b = unlayer<KL, GI, D, FLIP, DB, true>(f, lam, xb, xb2, tau, tk.x, tk.y);
+            const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
+            if (valid && tau == 0) gout[static_cast<size_t>(p) * M] = gb;
+            const float mu = kpowK(tk.y);
+            const float sc = exp2f(-0.5f * K);
+            float a;
+            if constexpr (RW) {
+                gen_stage_rw(f, D ? cfL : cf0, GPI(0), sc);
+                a = cgrad_stage_rw<false>(f, lam, D ? cfL : cf0, 0.0, cd.c0, 1.f);
+            } else if constexpr (D) {
+                gen_stage(f, pkL, ROW(0), sc);
+                a = cgrad_stage<false>(f, lam, pkL, ROW(0), cd.cut_min, 1.f);
+            } else {
+                gen_stage(f, pk0, ROW(0), sc);
+                a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
+            }
+            const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * a, red, tid);
+            if (valid && tau == 0) gout[0] = gc;
+        };
+
+        // Walk layers p-1 .. 2 back (both states exact at the start of each).  Layer p-1 is
+        // descending (stage 0 -> SL); the layers then alternate.  Undoing layer l leaves both
+        // states scaled by 1/mu_l (mu_l = |kappa_l|^K); D_l is then undone with a row scaled
+        // by mu_l, which restores them.
         int ly = p;
         for (;;) {
-            if (ly == 1) {
-                float a;
-                if constexpr (RW) a = cgrad_stage_rw<false>(f, lam, cf0, 0.0, cd.c0, 1.f);
-                else a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
-                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
-                if (valid && tau == 0) gout[0] = gc;
+            if (ly == 2) {
+                if constexpr (ODD) last_layer(std::true_type{});
                 break;
             }
-            {
-                float a;
-                if constexpr (RW) a = cgrad_stage_rw<true>(f, lam, cf0, GPI(ly - 1), cd.c0, mu);
-                else a = cgrad_stage<true>(f, lam, pk0, ROW(ly - 1), cd.cut_min, mu);
-                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
-                if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
-            }
+            float mu;
             {
                 const float2 tk = mix0[ly - 2];
                 const double b = unlayer<KL, GI, true, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
@@ -761,20 +907,16 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
                 mu = kpowK(tk.y);
             }
             --ly;
-            if (ly == 1) {
-                float a;
-                if constexpr (RW) a = cgrad_stage_rw<false>(f, lam, cfL, 0.0, cd.c0, 1.f);
-                else a = cgrad_stage<false>(f, lam, pkL, ROW(0), cd.cut_min, 1.f);
-                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
-                if (valid && tau == 0) gout[0] = gc;
-                break;
-            }
             {
                 float a;
                 if constexpr (RW) a = cgrad_stage_rw<true>(f, lam, cfL, GPI(ly - 1), cd.c0, mu);
                 else a = cgrad_stage<true>(f, lam, pkL, ROW(ly - 1), cd.cut_min, mu);
                 const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
                 if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
+            }
+            if (ly == 2) {
+                if constexpr (!ODD) last_layer(std::false_type{});
+                break;
             }
             {
                 const float2 tk = mix0[ly - 2];
@@ -784,6 +926,13 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
                 mu = kpowK(tk.y);
             }
             --ly;
+            {
+                float a;
+                if constexpr (RW) a = cgrad_stage_rw<true>(f, lam, cf0, GPI(ly - 1), cd.c0, mu);
+                else a = cgrad_stage<true>(f, lam, pk0, ROW(ly - 1), cd.cut_min, mu);
+                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
+                if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
+            }
         }
     }
 }
