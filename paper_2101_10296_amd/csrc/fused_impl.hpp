@@ -681,6 +681,15 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     constexpr int CUTB = (RW ? 4 : 1) * C::IPW * C::N;
     __shared__ __attribute__((aligned(16))) uint8_t cutl[CUTB < 16 ? 16 : CUTB];
     __shared__ double red[C::WG / 64];
+    // Deferred item sums (items of more than one wave): every value is summed within its
+    // wave at once (no barrier); the per-wave partials wait in LDS with the code of their
+    // destination and are summed over the item's waves and written at a flush, in the
+    // order item_sum uses, so one barrier pair serves up to NSUM values.
+    constexpr bool DEFER = C::TPI > 64;
+    constexpr int NSUM = 8;
+    __shared__ double dsum[DEFER ? NSUM : 1][DEFER ? C::WG / 64 : 1];
+    __shared__ int32_t dcode[DEFER ? NSUM : 1];
+    int nsum = 0;
     extern __shared__ float2 prow_all[];   // [IPW][p][rowcap] phase rows of every layer
 
     const int tid = threadIdx.x;
@@ -750,6 +759,40 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     // 1/|kappa|^K, the truncated last layer (qubits 0, 1) by 1/|kappa_p|^2.
     auto kpowK = [&](float k2) { return exp2f(0.5f * K * log2f(k2)); };
     const float k2p = mix0[p - 1].y;
+    // code 0: <Z0 Z1> of the item; code 1 + j: entry j of its gradient (gamma_1..p, beta_1..p)
+    auto put_out = [&](int code, double x) {
+        if (!valid) return;
+        if (code == 0) ea.zz[static_cast<size_t>(point) * ea.M + cd.orbit] = x;
+        else ea.g[(static_cast<size_t>(point) * 2 * p + (code - 1)) * ea.M + cd.orbit] = x;
+    };
+    auto flush = [&]() {
+        if constexpr (DEFER) {
+            __syncthreads();
+            if (tau == 0) {
+                const int w0 = tid >> 6;   // the item's first wave
+                for (int q = 0; q < nsum; ++q) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int w = 0; w < C::TPI / 64; ++w) x += dsum[q][w0 + w];
+                    put_out(dcode[q], x);
+                }
+            }
+            __syncthreads();
+            nsum = 0;
+        }
+    };
+    auto put = [&](int code, double x) {
+        if constexpr (DEFER) {
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
+            if ((tid & 63) == 0) dsum[nsum][tid >> 6] = x;
+            if (tid == 0) dcode[nsum] = code;
+            if (++nsum == NSUM) flush();
+        } else {
+            x = item_sum<KL, GI>(x, red, tid);
+            if (tau == 0) put_out(code, x);
+        }
+    };
 
     float2 f[A];
     // GRAD: psi after the mixer of layer p-1 at its true norm, kept for the adjoint (which
@@ -809,12 +852,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         const double pr = static_cast<double>(fmaf(f[r].x, f[r].x, f[r].y * f[r].y));
         zzp += (((r ^ (r >> 1)) & 1) ? -pr : pr);
     }
-    const double zz = item_sum<KL, GI>(HS * zzp, red, tid);
-    if (valid && tau == 0) ea.zz[static_cast<size_t>(point) * ea.M + cd.orbit] = zz;
+    put(0, HS * zzp);
 
     if constexpr (GRAD) {
-        const int M = ea.M;
-        double* gout = ea.g + static_cast<size_t>(point) * 2 * p * M + cd.orbit;
         float2 lam[A];
 #pragma unroll
         for (int r = 0; r < A; ++r) lam[r] = (((r ^ (r >> 1)) & 1) ? make_float2(-f[r].x, -f[r].y) : f[r]);
@@ -826,8 +866,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
 #pragma unroll
         for (int r = 0; r < A; ++r)
             if (!(r & 2)) xacc(acc, lam[r], lam[r | 2], f[r], f[r | 2]);
-        const double gbp = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(acc), red, tid);
-        if (valid && tau == 0) gout[static_cast<size_t>(2 * p - 1) * M] = gbp;
+        put(2 * p, HS * 2.0 * static_cast<double>(acc));
         const float mup = k2p;   // the undone last mixer leaves lambda scaled by 1/|kappa_p|^2
         if (p == 1) {
             // undo the last mixer on both states; the gamma_1 term (both carry 1/mu_p)
@@ -840,8 +879,8 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             float a;
             if constexpr (RW) a = cgrad_stage_rw<false>(f, lam, cf0, 0.0, cd.c0, 1.f);
             else a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
-            const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mup) * mup * a, red, tid);
-            if (valid && tau == 0) gout[0] = gc;
+            put(1, HS * 2.0 * static_cast<double>(mup) * mup * a);
+            flush();
             return;
         }
         // undo the last mixer on lambda; then D_p on lambda (the row scaled by mu_p restores
@@ -856,8 +895,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             float a;
             if constexpr (RW) a = cterm_lam_rw(lam, f1, cf0, GPI(p - 1), cd.c0, mup);
             else a = cterm_lam(lam, f1, pk0, ROW(p - 1), cd.cut_min, mup);
-            const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(a), red, tid);
-            if (valid && tau == 0) gout[static_cast<size_t>(p - 1) * M] = gc;
+            put(p, HS * 2.0 * static_cast<double>(a));
         }
 #pragma unroll
         for (int r = 0; r < A; ++r) f[r] = f1[r];
@@ -869,8 +907,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             constexpr bool D = decltype(dir)::value;
             const float2 tk = mix0[0];
             const double b = unlayer<KL, GI, D, FLIP, DB, true>(f, lam, xb, xb2, tau, tk.x, tk.y);
-            const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
-            if (valid && tau == 0) gout[static_cast<size_t>(p) * M] = gb;
+            put(1 + p, HS * 2.0 * b);
             const float mu = kpowK(tk.y);
             const float sc = exp2f(-0.5f * K);
             float a;
@@ -884,8 +921,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
                 gen_stage(f, pk0, ROW(0), sc);
                 a = cgrad_stage<false>(f, lam, pk0, ROW(0), cd.cut_min, 1.f);
             }
-            const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * a, red, tid);
-            if (valid && tau == 0) gout[0] = gc;
+            put(1, HS * 2.0 * static_cast<double>(mu) * a);
         };
 
         // Walk layers p-1 .. 2 back (both states exact at the start of each).  Layer p-1 is
@@ -902,8 +938,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             {
                 const float2 tk = mix0[ly - 2];
                 const double b = unlayer<KL, GI, true, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
-                const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
-                if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
+                put(1 + p + ly - 2, HS * 2.0 * b);
                 mu = kpowK(tk.y);
             }
             --ly;
@@ -911,8 +946,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
                 float a;
                 if constexpr (RW) a = cgrad_stage_rw<true>(f, lam, cfL, GPI(ly - 1), cd.c0, mu);
                 else a = cgrad_stage<true>(f, lam, pkL, ROW(ly - 1), cd.cut_min, mu);
-                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
-                if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
+                put(ly, HS * 2.0 * static_cast<double>(mu) * mu * a);
             }
             if (ly == 2) {
                 if constexpr (!ODD) last_layer(std::false_type{});
@@ -921,8 +955,7 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             {
                 const float2 tk = mix0[ly - 2];
                 const double b = unlayer<KL, GI, false, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
-                const double gb = item_sum<KL, GI>(HS * 2.0 * b, red, tid);
-                if (valid && tau == 0) gout[static_cast<size_t>(p + ly - 2) * M] = gb;
+                put(1 + p + ly - 2, HS * 2.0 * b);
                 mu = kpowK(tk.y);
             }
             --ly;
@@ -930,11 +963,11 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
                 float a;
                 if constexpr (RW) a = cgrad_stage_rw<true>(f, lam, cf0, GPI(ly - 1), cd.c0, mu);
                 else a = cgrad_stage<true>(f, lam, pk0, ROW(ly - 1), cd.cut_min, mu);
-                const double gc = item_sum<KL, GI>(HS * 2.0 * static_cast<double>(mu) * mu * a, red, tid);
-                if (valid && tau == 0) gout[static_cast<size_t>(ly - 1) * M] = gc;
+                put(ly, HS * 2.0 * static_cast<double>(mu) * mu * a);
             }
         }
     }
+    flush();
 }
 
 // ---------------------------------------------------------------- launcher
