@@ -182,6 +182,28 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
     for (int64_t i = 1; i < m; ++i)
         if (index.key[i] == index.key[i - 1]) fail(kEINVAL, "duplicate edge (" + std::to_string(index.key[i] / index.n) + "," + std::to_string(index.key[i] % index.n) + ")");
 
+    // ---- CSR adjacency with edge ids (neighbours in edge order)
+    std::vector<int64_t> off(static_cast<size_t>(n) + 1, 0);
+    for (int64_t e = 0; e < m; ++e) { off[P.u[e] + 1]++; off[P.v[e] + 1]++; }
+    for (int32_t i = 0; i < n; ++i) off[i + 1] += off[i];
+    std::vector<int32_t> nbr(2 * m);
+    std::vector<int64_t> nbr_e(2 * m);
+    {
+        std::vector<int64_t> pos(off.begin(), off.end() - 1);
+        for (int64_t e = 0; e < m; ++e) {
+            nbr[pos[P.u[e]]] = P.v[e]; nbr_e[pos[P.u[e]]++] = e;
+            nbr[pos[P.v[e]]] = P.u[e]; nbr_e[pos[P.v[e]]++] = e;
+        }
+    }
+    // edge id of {a, b}: a scan of the shorter neighbour list, the sorted index for long ones
+    auto edge_of = [&](int32_t a, int32_t b) -> int64_t {
+        if (off[a + 1] - off[a] > off[b + 1] - off[b]) std::swap(a, b);
+        if (off[a + 1] - off[a] > 32) return index.find(a, b);
+        for (int64_t j = off[a]; j < off[a + 1]; ++j)
+            if (nbr[j] == b) return nbr_e[j];
+        return -1;
+    };
+
     // ---- generators: verify, then union every edge with its image
     MinUnionFind uf(m);
     std::vector<char> seen(n);
@@ -193,7 +215,7 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
             seen[s[i]] = 1;
         }
         for (int64_t e = 0; e < m; ++e) {
-            const int64_t f = index.find(s[P.u[e]], s[P.v[e]]);
+            const int64_t f = edge_of(s[P.u[e]], s[P.v[e]]);
             if (f < 0) fail(kENOTAUT, "generator " + std::to_string(g) + " maps edge " + std::to_string(e) + " to a non-edge");
             if (std::memcmp(&P.w[e], &P.w[f], sizeof(double)) != 0)
                 fail(kENOTAUT, "generator " + std::to_string(g) + " does not preserve the weight of edge " + std::to_string(e));
@@ -216,20 +238,6 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
         P.total_weight += P.w[e];
     }
 
-    // ---- CSR adjacency with edge ids
-    std::vector<int64_t> off(static_cast<size_t>(n) + 1, 0);
-    for (int64_t e = 0; e < m; ++e) { off[P.u[e] + 1]++; off[P.v[e] + 1]++; }
-    for (int32_t i = 0; i < n; ++i) off[i + 1] += off[i];
-    std::vector<int32_t> nbr(2 * m);
-    std::vector<int64_t> nbr_e(2 * m);
-    {
-        std::vector<int64_t> pos(off.begin(), off.end() - 1);
-        for (int64_t e = 0; e < m; ++e) {
-            nbr[pos[P.u[e]]] = P.v[e]; nbr_e[pos[P.u[e]]++] = e;
-            nbr[pos[P.v[e]]] = P.u[e]; nbr_e[pos[P.v[e]]++] = e;
-        }
-    }
-
     // ---- light cones.  Every cone depends only on the graph, so the orbits are split into
     // contiguous ranges over threads; a failure reports the lowest failing orbit, as a
     // serial walk would.
@@ -237,7 +245,7 @@ void build_host_plan(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
     const int64_t M = static_cast<int64_t>(P.rep.size());
     P.cones.resize(static_cast<size_t>(M));
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int64_t nt = M >= 4096 ? std::min<int64_t>({8, hw, M / 1024}) : 1;
+    const int64_t nt = M >= 4096 ? std::min<int64_t>({16, hw, M / 1024}) : 1;
     std::vector<int64_t> fail_at(static_cast<size_t>(nt), -1);
     std::vector<PlanError> fail_err(static_cast<size_t>(nt));
     std::vector<char> no_mem(static_cast<size_t>(nt), 0);

@@ -341,39 +341,61 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
               " orbits; descriptors index both with 32-bit integers";
         return QAOA_EINVAL;
     }
+    // One device allocation holds every resident array: the ones with host data first (one
+    // copy), then the cut and C_tt tables, which kernels fill.
     const size_t ne = std::max<size_t>(ea.size(), 1);
-    QCHECK(hipMalloc(&P->d_cones, std::max<size_t>(cd.size(), 1) * sizeof(ConeDev)));
-    QCHECK(hipMalloc(&P->d_cut, std::max<int64_t>(cut_bytes, 16)));
-    QCHECK(hipMalloc(&P->d_W, std::max<size_t>(hp.W.size(), 1) * sizeof(double)));
-    QCHECK(hipMalloc(&P->d_ea, ne * sizeof(int32_t)));
-    QCHECK(hipMalloc(&P->d_eb, ne * sizeof(int32_t)));
-    QCHECK(hipMalloc(&P->d_ew, ne * sizeof(int32_t)));
-    QCHECK(hipMalloc(&P->d_hcones, std::max<size_t>(hc.size(), 1) * sizeof(ConeHbm)));
-    QCHECK(hipMalloc(&P->d_tt, std::max<int64_t>(tt_bytes, 16)));
-    QCHECK(hipMalloc(&P->d_inst_orbit, hp.inst_orbit.size() * sizeof(int64_t)));
-    QCHECK(hipMalloc(&P->d_inst_delta, hp.inst_delta.size() * sizeof(double)));
-    QCHECK(hipMemcpy(P->d_inst_orbit, hp.inst_orbit.data(), hp.inst_orbit.size() * sizeof(int64_t),
-                     hipMemcpyHostToDevice));
-    QCHECK(hipMemcpy(P->d_inst_delta, hp.inst_delta.data(), hp.inst_delta.size() * sizeof(double),
-                     hipMemcpyHostToDevice));
+    const std::vector<double> ones(hp.inst_delta.size(), 1.0);
+    size_t arena = 0;
+    auto place = [&](size_t bytes) {
+        const size_t o = arena;
+        arena += (std::max<size_t>(bytes, 16) + 255) & ~size_t{255};
+        return o;
+    };
+    const size_t o_cones = place(std::max<size_t>(cd.size(), 1) * sizeof(ConeDev));
+    const size_t o_W = place(std::max<size_t>(hp.W.size(), 1) * sizeof(double));
+    const size_t o_hcones = place(std::max<size_t>(hc.size(), 1) * sizeof(ConeHbm));
+    const size_t o_ea = place(ne * sizeof(int32_t));
+    const size_t o_eb = place(ne * sizeof(int32_t));
+    const size_t o_ew = place(ne * sizeof(int32_t));
+    const size_t o_io = place(hp.inst_orbit.size() * sizeof(int64_t));
+    const size_t o_id = place(hp.inst_delta.size() * sizeof(double));
+    const size_t o_ones = place(ones.size() * sizeof(double));
+    const size_t o_ewd = hp.realw ? place(std::max<size_t>(ewd.size(), 1) * sizeof(double)) : 0;
+    const size_t copied = arena;
+    const size_t o_cut = place(static_cast<size_t>(std::max<int64_t>(cut_bytes, 16)));
+    const size_t o_tt = place(static_cast<size_t>(std::max<int64_t>(tt_bytes, 16)));
     {
-        const std::vector<double> ones(hp.inst_delta.size(), 1.0);
-        QCHECK(hipMalloc(&P->d_ones, ones.size() * sizeof(double)));
-        QCHECK(hipMemcpy(P->d_ones, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<uint8_t> stage(copied, 0);
+        auto put = [&](size_t o, const void* src, size_t bytes) {
+            if (bytes) std::memcpy(stage.data() + o, src, bytes);
+        };
+        put(o_cones, cd.data(), cd.size() * sizeof(ConeDev));
+        put(o_W, hp.W.data(), hp.W.size() * sizeof(double));
+        put(o_hcones, hc.data(), hc.size() * sizeof(ConeHbm));
+        put(o_ea, ea.data(), ea.size() * sizeof(int32_t));
+        put(o_eb, eb.data(), eb.size() * sizeof(int32_t));
+        put(o_ew, ew.data(), ew.size() * sizeof(int32_t));
+        put(o_io, hp.inst_orbit.data(), hp.inst_orbit.size() * sizeof(int64_t));
+        put(o_id, hp.inst_delta.data(), hp.inst_delta.size() * sizeof(double));
+        put(o_ones, ones.data(), ones.size() * sizeof(double));
+        if (hp.realw) put(o_ewd, ewd.data(), ewd.size() * sizeof(double));
+        QCHECK(hipMalloc(&P->d_arena, arena));
+        QCHECK(hipMemcpy(P->d_arena, stage.data(), copied, hipMemcpyHostToDevice));
     }
-    if (M) QCHECK(hipMemcpy(P->d_cones, cd.data(), cd.size() * sizeof(ConeDev), hipMemcpyHostToDevice));
-    if (Mall) QCHECK(hipMemcpy(P->d_W, hp.W.data(), hp.W.size() * sizeof(double), hipMemcpyHostToDevice));
-    if (!hc.empty()) QCHECK(hipMemcpy(P->d_hcones, hc.data(), hc.size() * sizeof(ConeHbm), hipMemcpyHostToDevice));
-    if (!ea.empty()) {
-        QCHECK(hipMemcpy(P->d_ea, ea.data(), ea.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        QCHECK(hipMemcpy(P->d_eb, eb.data(), eb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        QCHECK(hipMemcpy(P->d_ew, ew.data(), ew.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
+    uint8_t* base = static_cast<uint8_t*>(P->d_arena);
+    P->d_cones = reinterpret_cast<ConeDev*>(base + o_cones);
+    P->d_W = reinterpret_cast<double*>(base + o_W);
+    P->d_hcones = reinterpret_cast<ConeHbm*>(base + o_hcones);
+    P->d_ea = reinterpret_cast<int32_t*>(base + o_ea);
+    P->d_eb = reinterpret_cast<int32_t*>(base + o_eb);
+    P->d_ew = reinterpret_cast<int32_t*>(base + o_ew);
+    P->d_inst_orbit = reinterpret_cast<int64_t*>(base + o_io);
+    P->d_inst_delta = reinterpret_cast<double*>(base + o_id);
+    P->d_ones = reinterpret_cast<double*>(base + o_ones);
+    P->d_ewd = hp.realw ? reinterpret_cast<double*>(base + o_ewd) : nullptr;
+    P->d_cut = base + o_cut;
+    P->d_tt = base + o_tt;
     if (hp.realw) {
-        // real weights stay resident: the device-memory passes sum each tile's coefficients
-        QCHECK(hipMalloc(&P->d_ewd, std::max<size_t>(ewd.size(), 1) * sizeof(double)));
-        if (!ewd.empty())
-            QCHECK(hipMemcpy(P->d_ewd, ewd.data(), ewd.size() * sizeof(double), hipMemcpyHostToDevice));
         QCHECK(launch_cut_tables_real(P->d_cones, M, P->d_ea, P->d_eb, P->d_ewd, reinterpret_cast<float*>(P->d_cut),
                                       nullptr));
         QCHECK(launch_tt_tables_real(P->d_hcones, static_cast<int64_t>(hc.size()), max_groups, P->d_ea, P->d_eb,
@@ -384,10 +406,7 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
                                 P->d_ew, P->d_tt, nullptr));
     }
     QCHECK(hipDeviceSynchronize());
-    P->resident_bytes = cd.size() * sizeof(ConeDev) + static_cast<size_t>(cut_bytes) + hp.W.size() * sizeof(double) +
-                        hc.size() * sizeof(ConeHbm) + static_cast<size_t>(tt_bytes) + 3 * ne * sizeof(int32_t) +
-                        hp.inst_orbit.size() * sizeof(int64_t) + 2 * hp.inst_delta.size() * sizeof(double) +
-                        ewd.size() * sizeof(double);
+    P->resident_bytes = arena;
     P->device = dev;
     P->dev_ready = true;
     return QAOA_OK;
@@ -761,42 +780,33 @@ void release_device(qaoa_plan_s* P) {
     P->timed.clear();
     if (!P->dev_ready && !P->d_phase) return;
     hipDeviceSynchronize();
-    hipFree(P->d_cones);
-    hipFree(P->d_cut);
-    hipFree(P->d_W);
+    hipFree(P->d_arena);
     hipFree(P->d_phase);
     hipFree(P->d_mix);
     hipFree(P->d_zz);
     hipFree(P->d_g);
-    hipFree(P->d_hcones);
-    hipFree(P->d_ea);
-    hipFree(P->d_eb);
-    hipFree(P->d_ew);
-    hipFree(P->d_tt);
     hipFree(P->d_phi);
     hipFree(P->d_lam);
     hipFree(P->d_gpart);
-    hipFree(P->d_ewd);
-    P->d_ewd = nullptr;
-    hipFree(P->d_inst_orbit);
-    hipFree(P->d_inst_delta);
-    hipFree(P->d_ones);
-    P->d_inst_orbit = nullptr;
-    P->d_inst_delta = nullptr;
-    P->d_ones = nullptr;
-    P->d_hcones = nullptr;
-    P->d_ea = P->d_eb = P->d_ew = nullptr;
-    P->d_tt = nullptr;
-    P->d_phi = P->d_lam = nullptr;
-    P->d_gpart = nullptr;
-    P->cap_phi = P->cap_lam = P->cap_gpart = 0;
+    P->d_arena = nullptr;
     P->d_cones = nullptr;
     P->d_cut = nullptr;
     P->d_W = nullptr;
+    P->d_hcones = nullptr;
+    P->d_ea = P->d_eb = P->d_ew = nullptr;
+    P->d_ewd = nullptr;
+    P->d_tt = nullptr;
+    P->d_inst_orbit = nullptr;
+    P->d_inst_delta = nullptr;
+    P->d_ones = nullptr;
+    P->d_phi = P->d_lam = nullptr;
+    P->d_gpart = nullptr;
+    P->cap_phi = P->cap_lam = P->cap_gpart = 0;
     P->d_phase = nullptr;
     P->d_mix = nullptr;
     P->d_zz = nullptr;
     P->d_g = nullptr;
+    P->cap_phase = P->cap_mix = P->cap_zz = P->cap_g = 0;
     P->dev_ready = false;
 }
 

@@ -15,7 +15,8 @@ struct qaoa_plan_s {
     qaoa::HostPlan hp;
     qaoa::PlanOptions opt;
 
-    // ---- device-resident plan data (built on the first energy call)
+    // ---- device-resident plan data (built on the first energy call, one allocation: d_arena)
+    void* d_arena = nullptr;
     int device = -1;
     bool dev_ready = false;
     struct Group {
