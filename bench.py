@@ -29,14 +29,14 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "9ad233080ddcb4cde45669389ebc0a9c4bf36e418c120b15f2ba4b5ffc286e49",
-               "counted_over_algorithmic": 1.005}
+HBM_TRAFFIC = {"sources_sha256": "8e3b3f6644b881988c3505540a9a989cc05fcc003f04de6fd4910cbb56b9ffbb",
+               "counted_over_algorithmic": 1.003}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
 # item (cut tables and phase rows read, five FP64 results written).
-FUSED_TRAFFIC = {"sources_sha256": "8a670b0680593c7579cc1fa80ebf6cecd2701932f50ce1ce59200fd8798c2cb1",
-                 "bytes_per_item": 297.5}
+FUSED_TRAFFIC = {"sources_sha256": "061d0a49400c4171a2c35259fe1af608145deb1340b868072fd6f209cd2c364e",
+                 "bytes_per_item": 298.6}
 
 
 def sources_sha256(files) -> str:

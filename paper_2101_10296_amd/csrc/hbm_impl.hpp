@@ -101,11 +101,11 @@ struct PassArgs {
 };
 
 // Register configurations (measured on MI355X over 20-30-qubit cones):
-//   CF 0  forward, one tile:        32 amplitudes per thread, 256 threads (generation and
-//                                   final passes of groups >= 1)
+//   CF 0  forward, one tile:        32 amplitudes per thread, 256 threads (mixer-only passes
+//                                   of groups >= 1)
 //   CF 1  one tile:                 16 per state, 512 threads, <= 128 VGPRs (two per CU):
-//                                   adjoint passes, and the forward mixer passes, which
-//                                   run faster at this occupancy than in CF 0
+//                                   adjoint passes, and the forward boundary passes (two
+//                                   mixers and a phase), which run faster at this occupancy
 //   CF 2  forward, tile pair:       16 per tile, 512 threads, <= 128 VGPRs
 //   CF 3  adjoint, tile pair:       16 per state and tile, 512 threads, one workgroup per CU
 //         (four states in registers; fewer amplitudes per thread spill at 1024 threads)
@@ -127,7 +127,7 @@ struct Hz {
 };
 
 __host__ __device__ constexpr int pass_cf(int kind, bool g0) {
-    if (!g0 && (kind == FWD_MIX || kind == FWD_BND_MIX)) return 1;
+    if (!g0 && kind == FWD_BND_MIX) return 1;
     return (kind >= GR_GEN_FINAL ? 1 : 0) + ((g0 && kind != FWD_GEN_FINAL && kind != GR_GEN_FINAL) ? 2 : 0);
 }
 
