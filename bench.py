@@ -84,15 +84,20 @@ def flops_fwd_adj(k: int, p: int) -> float:
     Mixer: 6 flop per amplitude per qubit (c*a - i*s*b); phase: 6 (complex multiply);
     <Z0 Z1>: 4; Im<lambda|X_j|psi>: 4 per amplitude per qubit; Im<lambda|C|psi>: 5.
     Forward: D_1|+> (2), p-1 full layers (6k + 6), last two-qubit mixer (12), zz (4).
-    Adjoint: beta_p inner products (8), undo last mixer on two states (24), p gamma inner
-    products (5), p-1 phases undone on two states (12), p-1 full layers undone on two
-    states with their inner products (16k).
+    Adjoint (p >= 2): beta_p inner products (8), undo of the last mixer on lambda (12; psi
+    before D_p is kept), p gamma inner products (5), D_p undone on lambda (6) and the other
+    p-2 phases on two states (12), p-1 full layers undone on two states with their inner
+    products (16k; the last stage of layer 1 leaves psi alone, which is not counted).
+    p = 1: beta_1 (8), the last mixer undone on two states (24), gamma_1 (5).
     Per stored amplitude: cones of k >= 3 qubits keep only the half of the state with
     qubit k-1 = 0 (the state is invariant under flipping every qubit), 2^(k-1) amplitudes.
     """
     n = float(1 << (k - 1 if k >= 3 else k))
     fwd = 2 + (p - 1) * (6 * k + 6) + 12 + 4
-    adj = 8 + 24 + 5 * p + 12 * (p - 1) + 16 * k * (p - 1)
+    if p == 1:
+        adj = 8 + 24 + 5
+    else:
+        adj = 8 + 12 + 5 * p + 6 + 12 * (p - 2) + 16 * k * (p - 1)
     return n * (fwd + adj)
 
 

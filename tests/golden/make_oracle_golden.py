@@ -26,7 +26,8 @@ import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
 # Full cases: energy, per-orbit <Z_u Z_v> and gradient of every orbit.
-# name -> (graph family, its arguments, p, reduce, number of angle points, angle seed)
+# name -> (graph family, its arguments, p, reduce, number of angle points, angle seed
+#          [, name of the workloads function giving the edge weights])
 CASES = {
     "c1_rand3_n16_p1": ("random_regular", [16, 3, 0], 1, False, 1, 100),
     # two pass groups of stored qubits (23-qubit cone: 22 stored qubits) at p = 2
@@ -37,6 +38,9 @@ CASES = {
     # p = 3 (four such cones)
     "spider5_6_p2": ("spider_pair", [5, 6], 2, True, 2, 611),
     "spider5_6_p3": ("spider_pair", [5, 6], 3, True, 2, 612),
+    # the same graph with weights sqrt(deg u + deg v) (no common unit, kept by the
+    # generators: real cut values) at p = 2
+    "spider5_6_p2_rootw": ("spider_pair", [5, 6], 2, True, 2, 613, "degree_root_weights"),
     # random 3-regular n = 1000, p = 2 (1500 cones of 10-14 qubits): energy and gradient at
     # all 64 angle points of that workload (its per-term values are not stored)
     "c3_rand3_n1000_p2_all": ("random_regular", [1000, 3, 3], 2, False, 64, 300),
@@ -62,11 +66,16 @@ def graph_of(family, args):
     return getattr(W, family)(*args)
 
 
+def weights_of(name, g):
+    spec = CASES[name]
+    return getattr(W, spec[6])(g) if len(spec) > 6 else None
+
+
 def _full_task(args):
     name, i = args
-    fam, gargs, p, reduce, P, seed = CASES[name]
+    fam, gargs, p, reduce, P, seed = CASES[name][:6]
     g = graph_of(fam, gargs)
-    ref = oracle.plan(g.n, g.edges, None, g.gens() if reduce else None, p, reduce=reduce, max_k=30)
+    ref = oracle.plan(g.n, g.edges, weights_of(name, g), g.gens() if reduce else None, p, reduce=reduce, max_k=30)
     ga, be = W.draw_angles(P, p, seed)
     t = time.time()
     E, dg, db, zz = oracle.energy_grad(ref, ga[i:i + 1], be[i:i + 1])
@@ -120,11 +129,12 @@ def main():
     done = dict(zip([t[1] for t in tasks], res))
     for n in names:
         if n in CASES:
-            fam, gargs, p, reduce, P, seed = CASES[n]
+            fam, gargs, p, reduce, P, seed = CASES[n][:6]
             g = graph_of(fam, gargs)
-            ref = oracle.plan(g.n, g.edges, None, g.gens() if reduce else None, p, reduce=reduce, max_k=30)
+            ref = oracle.plan(g.n, g.edges, weights_of(n, g), g.gens() if reduce else None, p, reduce=reduce, max_k=30)
             parts = [done[(n, i)] for i in range(P)]
             case = dict(name=n, family=fam, args=gargs, p=p, reduce=reduce, points=P, seed=seed,
+                        weights=CASES[n][6] if len(CASES[n]) > 6 else None,
                         rep=[int(x) for x in ref["rep"]], W=[float(x) for x in ref["W"]],
                         energy=np.concatenate([r[0] for r in parts]).tolist(),
                         zz=None if n in NO_TERMS else np.concatenate([r[3] for r in parts]).tolist(),

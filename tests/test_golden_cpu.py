@@ -25,7 +25,8 @@ def cases(kind="cases"):
 def test_stored_case_consistent(c):
     g = getattr(W, c["family"])(*c["args"])
     gens = g.gens() if c["reduce"] else None
-    ref = oracle.plan(g.n, g.edges, None, gens, c["p"], reduce=c["reduce"], max_k=30)
+    w = getattr(W, c["weights"])(g) if c.get("weights") else None
+    ref = oracle.plan(g.n, g.edges, w, gens, c["p"], reduce=c["reduce"], max_k=30)
     assert [int(x) for x in ref["rep"]] == c["rep"]
     np.testing.assert_array_equal(ref["W"], c["W"])
     ga, be = W.draw_angles(c["points"], c["p"], c["seed"])

@@ -127,6 +127,9 @@ STORED = {
     # four 25-qubit cones at p = 3: every multi-pass kind, both snake directions
     "spider5_6_p3": ({FWD_GEN_MIX, FWD_MIX, FWD_BND_MIX, FWD_BND_FINAL},
                      {FWD_GEN_MIX, FWD_MIX, FWD_BND_MIX, GR_BND_FINAL, RV_MIX, RV_BND_MIX, RV_GEN_MIX}),
+    # the 25-qubit cone with real weights sqrt(deg u + deg v) (kept by the generators)
+    "spider5_6_p2_rootw": ({FWD_GEN_MIX, FWD_MIX, FWD_BND_FINAL},
+                           {FWD_GEN_MIX, FWD_MIX, GR_BND_FINAL, RV_MIX, RV_GEN_MIX}),
 }
 
 
@@ -139,11 +142,13 @@ def test_stored_oracle_cases(Q, name, ckpt):
     # from stored checkpoints (ckpt 1)
     c = _golden_cases()[name]
     g = getattr(W, c["family"])(*c["args"])
+    w = getattr(W, c["weights"])(g) if c.get("weights") else None
     ga, be = W.draw_angles(c["points"], c["p"], c["seed"])
-    pl = Q.Plan(g.n, g.edges, p=c["p"], generators=g.gens() if c["reduce"] else None, reduce=c["reduce"],
-                checkpoint_mode=ckpt)
+    pl = Q.Plan(g.n, g.edges, p=c["p"], weights=w, generators=g.gens() if c["reduce"] else None,
+                reduce=c["reduce"], checkpoint_mode=ckpt)
     eo, rep, _ = pl.orbits()
     assert list(rep) == c["rep"]
+    assert pl.info()["real_weights"] == (1 if w is not None else 0)
     kinds_fwd, kinds_grad = STORED[name]
     E, zz = pl.energy(dev(ga), dev(be), term_zz=True)
     ran = {i for i, n in enumerate(pl.info()["pass_launches"]) if n}
@@ -153,7 +158,7 @@ def test_stored_oracle_cases(Q, name, ckpt):
     assert ran == kinds_grad, ran
     assert (pl.info()["checkpointed_classes"] > 0) == bool(ckpt)
     zz = zz.cpu().numpy()
-    Wt = float(np.sum(c["W"]))
+    Wt = float(np.sum(np.abs(c["W"])))
     assert np.abs(zz - np.array(c["zz"])).max() <= ZZ_TOL
     assert np.abs(E.cpu().numpy() - np.array(c["energy"])).max() <= ZZ_TOL * Wt / 2
     assert np.abs(E2.cpu().numpy() - np.array(c["energy"])).max() <= ZZ_TOL * Wt / 2

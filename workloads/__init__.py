@@ -19,6 +19,7 @@ from .graphs import (  # noqa: F401
     star,
     spider_pair,
     relabel,
+    degree_root_weights,
 )
 from .angles import draw_angles  # noqa: F401
 from .configs import workload  # noqa: F401

@@ -280,3 +280,10 @@ def relabel(g: Graph, perm: np.ndarray) -> Graph:
     out.edge_map = np.empty(g.m, np.int64)  # type: ignore[attr-defined]
     out.edge_map[order] = np.arange(g.m)    # type: ignore[attr-defined]
     return out
+
+
+def degree_root_weights(g: Graph) -> np.ndarray:
+    """Edge weights sqrt(deg u + deg v): irrational for most edges (no common unit) and kept
+    by every automorphism, so a weighted instance with the graph's own edge-colour symmetry."""
+    deg = np.bincount(g.edges.ravel(), minlength=g.n)
+    return np.sqrt((deg[g.edges[:, 0]] + deg[g.edges[:, 1]]).astype(np.float64))
