@@ -118,9 +118,11 @@ typedef struct {
                                      fastest for the rest of the process, per (device
                                      architecture, class, k, p, gradient, real weights);
                                      qaoa_tuning_report lists the choices.  0 = fixed defaults;
-                                     2, 3, 4 = workgroup layout 0 (default), 1 (one register bit
-                                     fewer per stage), 2 (workgroups of >= 256 threads) wherever
-                                     it applies, without timing (tests, experiments) */
+                                     2, 3, 4, 5 = workgroup layout 0 (default), 1 (one register
+                                     bit fewer per stage), 2 (workgroups of >= 256 threads),
+                                     3 (14-qubit adjoint: register/lane exchange layouts, one LDS
+                                     transpose per layer) wherever it applies, without timing
+                                     (tests, experiments) */
 } qaoa_plan_opts;
 
 typedef struct {

@@ -73,7 +73,7 @@ qaoa_status plan_options(const qaoa_plan_opts* opts, qaoa::PlanOptions& o) {
         o.profile = opts->profile;
         o.graph = opts->graph;
         o.tune = opts->tune;
-        if (o.tune < 0 || o.tune > 4) return set_err(QAOA_EINVAL, "tune must be 0, 1 or 2-4");
+        if (o.tune < 0 || o.tune > 5) return set_err(QAOA_EINVAL, "tune must be 0, 1 or 2-5");
         if (o.mem_budget_bytes < 0) return set_err(QAOA_EINVAL, "mem_budget_bytes must be >= 0");
         if (o.reduce != 0 && o.reduce != 1) return set_err(QAOA_EINVAL, "reduce must be 0 or 1");
         if (o.graph != 0 && o.graph != 1) return set_err(QAOA_EINVAL, "graph must be 0 or 1");

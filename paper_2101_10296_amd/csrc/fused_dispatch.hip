@@ -44,7 +44,7 @@ std::vector<int> fused_variants(int K, bool grad) {
     std::vector<int> v{0};
     auto add = [&](auto kc) {
         constexpr int KK = decltype(kc)::value;
-        for (int x = 1; x <= 2; ++x)
+        for (int x = 1; x <= 3; ++x)
             if (fused_variant_ok<KK>(grad, x)) v.push_back(x);
     };
     switch (K) {

@@ -42,6 +42,7 @@ namespace qaoa {
 //   0  the default: 5 register bits per stage forward, 4 adjoint; workgroups of >= 64 threads
 //   1  one register bit fewer per stage (qubits per LDS pass): more threads per item
 //   2  workgroups of >= 256 threads (more cones per workgroup for small cones)
+//   3  the 14-qubit adjoint kernel in the exchange layouts (one LDS transpose per layer)
 #ifndef QAOA_FUSED_AB_GRAD
 #define QAOA_FUSED_AB_GRAD 4
 #endif
@@ -637,6 +638,353 @@ __device__ __forceinline__ double unlayer(float2 (&f)[A], float2 (&l)[A], float2
     return acc;
 }
 
+// ---------------------------------------------------------------- exchange layouts
+// Layout variant 3 of the 14-qubit adjoint kernel (13 stored qubits, 16 amplitudes per
+// state and thread, 512 threads: lane bits 0-5, wave bits 6-8).  A layout names the qubit
+// of every register bit and thread bit.  Four layouts per layer:
+//   X0  registers q0-q3,   lanes q4-q9,             waves q10-q12
+//   X0s registers q8 q9 q2 q3, lanes q4-q7 q0 q1,   waves q10-q12
+//   X1  registers q4-q7,   lanes q12 q0 q1 q2 q10 q11, waves q3 q8 q9
+//   X1s registers q10 q11 q6 q7, lanes q12 q0 q1 q2 q4 q5, waves q3 q8 q9
+// X0 <-> X0s and X1 <-> X1s exchange register bits 0, 1 with lane bits 4, 5 inside each
+// wave (v_permlane16_swap / v_permlane32_swap: no LDS, no barrier); X0s <-> X1 is the one
+// LDS transpose of a layer, and the dropped qubit's butterfly rides on it.  A layer mixes
+// q0-q3 in X0, q8 q9 in X0s, q4 q5 in X1, and q10 q11 q6 q7 plus q12 (lane bit 0, across
+// lanes) in X1s.  X0 holds q0, q1 in register bits 0, 1 like stage 0 of the rotated layouts
+// (final mixer, <Z0 Z1>), and X1s stands where their last stage stands.  The lane-bit qubits
+// of the transposed layouts (q4-q7 and q12 q0 q1 q2) have padding weights 1, 2, 4, 8 mod 16,
+// so each group of 16 lanes hits 16 distinct bank pairs, complement partners included.
+struct LayX0 {
+    static constexpr int reg[4] = {0, 1, 2, 3};
+    static constexpr int thr[9] = {4, 5, 6, 7, 8, 9, 10, 11, 12};
+};
+struct LayX0s {
+    static constexpr int reg[4] = {8, 9, 2, 3};
+    static constexpr int thr[9] = {4, 5, 6, 7, 0, 1, 10, 11, 12};
+};
+struct LayX1 {
+    static constexpr int reg[4] = {4, 5, 6, 7};
+    static constexpr int thr[9] = {12, 0, 1, 2, 10, 11, 3, 8, 9};
+};
+struct LayX1s {
+    static constexpr int reg[4] = {10, 11, 6, 7};
+    static constexpr int thr[9] = {12, 0, 1, 2, 4, 5, 3, 8, 9};
+};
+template <class L>
+__host__ __device__ constexpr uint32_t lay_r(int r) {
+    uint32_t q = 0;
+    for (int i = 0; i < 4; ++i)
+        if ((r >> i) & 1) q |= 1u << L::reg[i];
+    return q;
+}
+template <class L>
+__device__ __forceinline__ uint32_t lay_t(uint32_t tau) {
+    uint32_t q = 0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+        if ((tau >> j) & 1u) q |= 1u << L::thr[j];
+    return q;
+}
+
+// Exchange register bits 0, 1 with lane bits 4, 5 (an involution: X0 <-> X0s, X1 <-> X1s).
+__device__ __forceinline__ void xswap(float& a, float& b, bool w32) {
+    const unsigned x = __float_as_uint(a), y = __float_as_uint(b);
+    if (w32) {
+        const auto s = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        a = __uint_as_float(s[0]);
+        b = __uint_as_float(s[1]);
+    } else {
+        const auto s = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        a = __uint_as_float(s[0]);
+        b = __uint_as_float(s[1]);
+    }
+}
+template <int A>
+__device__ __forceinline__ void lane_exchange(float2 (&v)[A]) {
+#pragma unroll
+    for (int r = 0; r < A; ++r)
+        if (!(r & 1)) { xswap(v[r].x, v[r | 1].x, false); xswap(v[r].y, v[r | 1].y, false); }
+#pragma unroll
+    for (int r = 0; r < A; ++r)
+        if (!(r & 2)) { xswap(v[r].x, v[r | 2].x, true); xswap(v[r].y, v[r | 2].y, true); }
+}
+
+// Mixer on the register bits in MASK, and (LANE) on lane bit 0 across lanes.
+template <int MASK, bool LANE, int A>
+__device__ __forceinline__ void xmix(float2 (&v)[A], float t) {
+    if constexpr (LANE) {
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 q = lane_x1(v[r]);
+            v[r] = make_float2(fmaf(t, q.y, v[r].x), fmaf(-t, q.x, v[r].y));
+            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!((MASK >> i) & 1)) continue;
+        int nb = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                bfly(v[r], v[r | (1 << i)], t);
+                if ((++nb & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Undo of xmix on psi and lambda with the terms of Im <lambda| X_j |psi> (as unmix_stage2).
+template <int MASK, bool LANE, int A>
+__device__ __forceinline__ float xunmix2(float2 (&f)[A], float2 (&l)[A], float t, float k2, float& w) {
+    float acc = 0.f;
+    if constexpr (LANE) {
+        float a = 0.f;
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 fq = lane_x1(f[r]);
+            const float2 lq = lane_x1(l[r]);
+            cacc(a, 1.f, l[r], fq);
+            f[r] = make_float2(fmaf(-t, fq.y, f[r].x), fmaf(t, fq.x, f[r].y));
+            l[r] = make_float2(fmaf(-t, lq.y, l[r].x), fmaf(t, lq.x, l[r].y));
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        acc = w * a;
+        w *= k2;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!((MASK >> i) & 1)) continue;
+        float a0 = 0.f, a1 = 0.f;
+        int np = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                const int r2 = r | (1 << i);
+                bfly(f[r], f[r2], -t);
+                bfly(l[r], l[r2], -t);
+                if (np++ & 1) xacc(a1, l[r], l[r2], f[r], f[r2]);
+                else xacc(a0, l[r], l[r2], f[r], f[r2]);
+                if ((np & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        w *= k2;
+        acc = fmaf(w, a0 + a1, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// The last step of the undo of layer 1 (as unmix_stage_last): every term at the entry,
+// then the mixer undone on lambda alone.
+template <int MASK, bool LANE, int A>
+__device__ __forceinline__ float xunmix_last(const float2 (&f)[A], float2 (&l)[A], float t, float w) {
+    float a0 = 0.f, a1 = 0.f;
+    if constexpr (LANE) {
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            if (r & 1) cacc(a1, 1.f, l[r], lane_x1(f[r]));
+            else cacc(a0, 1.f, l[r], lane_x1(f[r]));
+            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!((MASK >> i) & 1)) continue;
+        int np = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                const int r2 = r | (1 << i);
+                if (np++ & 1) xacc(a1, l[r], l[r2], f[r], f[r2]);
+                else xacc(a0, l[r], l[r2], f[r], f[r2]);
+                if ((np & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (LANE) {
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 lq = lane_x1(l[r]);
+            l[r] = make_float2(fmaf(-t, lq.y, l[r].x), fmaf(t, lq.x, l[r].y));
+            if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!((MASK >> i) & 1)) continue;
+        int nb = 0;
+#pragma unroll
+        for (int r = 0; r < A; ++r)
+            if (!(r & (1 << i))) {
+                bfly(l[r], l[r | (1 << i)], -t);
+                if ((++nb & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return w * (a0 + a1);
+}
+
+// LDS transpose FROM -> TO with the dropped qubit's butterfly (partner: the complement over
+// the stored bits, thread ~tau, register A-1-r), as xpose_flip.
+template <class LF, class LT, int A>
+__device__ __forceinline__ void xl_flip(float2 (&v)[A], float2* xb, uint32_t tau, float t) {
+    constexpr uint32_t TM = 511u;
+    float2* pf = xb + opaque_u32(pad<4>(lay_t<LF>(tau)));
+    const float2* pt = xb + opaque_u32(pad<4>(lay_t<LT>(tau)));
+    const float2* pc = xb + opaque_u32(pad<4>(lay_t<LT>(~tau & TM)));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) pf[pad<4>(lay_r<LF>(r))] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+        const float2 a = pt[pad<4>(lay_r<LT>(r))];
+        const float2 b = pc[pad<4>(lay_r<LT>(A - 1 - r))];
+        v[r] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// LDS transpose FROM -> TO of psi and lambda undoing the dropped qubit's butterfly; returns
+// the thread's share of Im <lambda| X_(K-1) |psi> on the values before the undo (as
+// xpose2_unflip_dual / xpose2_unflip).
+template <class LF, class LT, bool DB, int A>
+__device__ __forceinline__ float xl_unflip2(float2 (&f)[A], float2 (&l)[A], float2* xa, float2* xc, uint32_t tau,
+                                            float t) {
+    constexpr uint32_t TM = 511u;
+    const uint32_t of = opaque_u32(pad<4>(lay_t<LF>(tau)));
+    const uint32_t ot = opaque_u32(pad<4>(lay_t<LT>(tau)));
+    const uint32_t oc = opaque_u32(pad<4>(lay_t<LT>(~tau & TM)));
+    float acc = 0.f;
+    if constexpr (DB) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            xa[of + pad<4>(lay_r<LF>(r))] = f[r];
+            xc[of + pad<4>(lay_r<LF>(r))] = l[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 fo = xa[ot + pad<4>(lay_r<LT>(r))];
+            const float2 fq = xa[oc + pad<4>(lay_r<LT>(A - 1 - r))];
+            const float2 lo = xc[ot + pad<4>(lay_r<LT>(r))];
+            const float2 lq = xc[oc + pad<4>(lay_r<LT>(A - 1 - r))];
+            cacc(acc, 1.f, lo, fq);
+            l[r] = make_float2(fmaf(-t, lq.y, lo.x), fmaf(t, lq.x, lo.y));
+            f[r] = make_float2(fmaf(-t, fq.y, fo.x), fmaf(t, fq.x, fo.y));
+            if ((r & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        float2 fp[A];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < A; ++r) xa[of + pad<4>(lay_r<LF>(r))] = f[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            f[r] = xa[ot + pad<4>(lay_r<LT>(r))];
+            fp[r] = xa[oc + pad<4>(lay_r<LT>(A - 1 - r))];
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < A; ++r) xa[of + pad<4>(lay_r<LF>(r))] = l[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < A; ++r) {
+            const float2 lo = xa[ot + pad<4>(lay_r<LT>(r))];
+            const float2 lq = xa[oc + pad<4>(lay_r<LT>(A - 1 - r))];
+            cacc(acc, 1.f, lo, fp[r]);
+            l[r] = make_float2(fmaf(-t, lq.y, lo.x), fmaf(t, lq.x, lo.y));
+            f[r] = make_float2(fmaf(-t, fp[r].y, f[r].x), fmaf(t, fp[r].x, f[r].y));
+            if ((r & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return acc;
+}
+
+// One forward layer in the exchange layouts: descending X1s -> X1 -> X0s -> X0, ascending
+// the reverse; the dropped qubit on the transpose.
+template <bool DESC, int A>
+__device__ __forceinline__ void xfwd_layer(float2 (&f)[A], float2* xb, uint32_t tau, float t) {
+    static_assert(A == 16, "exchange layouts hold 16 amplitudes per thread");
+    if constexpr (DESC) {
+        xmix<0xF, true>(f, t);
+        lane_exchange(f);
+        xmix<0x3, false>(f, t);
+        xl_flip<LayX1, LayX0s>(f, xb, tau, t);
+        xmix<0x3, false>(f, t);
+        lane_exchange(f);
+        xmix<0xF, false>(f, t);
+    } else {
+        xmix<0xF, false>(f, t);
+        lane_exchange(f);
+        xmix<0x3, false>(f, t);
+        xl_flip<LayX0s, LayX1>(f, xb, tau, t);
+        xmix<0x3, false>(f, t);
+        lane_exchange(f);
+        xmix<0xF, true>(f, t);
+    }
+}
+
+// Undo a forward layer of direction DESC on psi and lambda; returns the thread's share of
+// Im <lambda| sum_j X_j |psi>.  LAST: the undo of layer 1 (xunmix_last in its last layout).
+template <bool DESC, bool DB, bool LAST, int A>
+__device__ __forceinline__ double xunlayer(float2 (&f)[A], float2 (&l)[A], float2* xb, float2* xb2, uint32_t tau,
+                                           float t, float k2) {
+    static_assert(A == 16, "exchange layouts hold 16 amplitudes per thread");
+    double acc = 0.0;
+    float w = 1.f;
+    if constexpr (DESC) {   // X0 -> X0s -> X1 -> X1s
+        acc += static_cast<double>(xunmix2<0xF, false>(f, l, t, k2, w));
+        lane_exchange(f);
+        lane_exchange(l);
+        acc += static_cast<double>(xunmix2<0x3, false>(f, l, t, k2, w));
+        acc += static_cast<double>(w * xl_unflip2<LayX0s, LayX1, DB>(f, l, xb, DB ? xb2 : xb, tau, t));
+        w *= k2;
+        acc += static_cast<double>(xunmix2<0x3, false>(f, l, t, k2, w));
+        lane_exchange(f);
+        lane_exchange(l);
+        if constexpr (LAST) acc += static_cast<double>(xunmix_last<0xF, true>(f, l, t, w));
+        else acc += static_cast<double>(xunmix2<0xF, true>(f, l, t, k2, w));
+    } else {                // X1s -> X1 -> X0s -> X0
+        acc += static_cast<double>(xunmix2<0xF, true>(f, l, t, k2, w));
+        lane_exchange(f);
+        lane_exchange(l);
+        acc += static_cast<double>(xunmix2<0x3, false>(f, l, t, k2, w));
+        acc += static_cast<double>(w * xl_unflip2<LayX1, LayX0s, DB>(f, l, xb, DB ? xb2 : xb, tau, t));
+        w *= k2;
+        acc += static_cast<double>(xunmix2<0x3, false>(f, l, t, k2, w));
+        lane_exchange(f);
+        lane_exchange(l);
+        if constexpr (LAST) acc += static_cast<double>(xunmix_last<0xF, false>(f, l, t, w));
+        else acc += static_cast<double>(xunmix2<0xF, false>(f, l, t, k2, w));
+    }
+    return acc;
+}
+
+// Cut values of the thread's amplitudes in layout L, packed four bytes per register, or
+// floats (real weights).
+template <class L, int A>
+__device__ __forceinline__ void xload_cuts(uint32_t (&pk)[(A + 3) / 4], const uint8_t* cut, uint32_t tau) {
+    const uint8_t* cb = cut + lay_t<L>(tau);
+#pragma unroll
+    for (int w = 0; w < (A + 3) / 4; ++w) pk[w] = 0u;
+#pragma unroll
+    for (int r = 0; r < A; ++r) pk[r >> 2] |= static_cast<uint32_t>(cb[lay_r<L>(r)]) << (8 * (r & 3));
+}
+template <class L, int A>
+__device__ __forceinline__ void xload_cuts_rw(float (&cf)[A], const float* cut, uint32_t tau) {
+    const float* cb = cut + lay_t<L>(tau);
+#pragma unroll
+    for (int r = 0; r < A; ++r) cf[r] = cb[lay_r<L>(r)];
+}
+
 // Sum over the threads of one item (fixed order, identical result in every lane).
 template <int K, int G>
 __device__ __forceinline__ double item_sum(double x, double* red, int tid) {
@@ -676,6 +1024,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     constexpr double HS = FLIP ? 2.0 : 1.0;
     using C = Fz<KL, GI>;
     constexpr int A = C::A;
+    // variant 3: the exchange layouts (14-qubit adjoint only)
+    constexpr bool XL = V == 3;
+    static_assert(!XL || (KL == 13 && GRAD && A == 16 && C::TPI == 512), "exchange layouts: 14-qubit adjoint only");
     __shared__ float2 xbuf[C::S > 1 ? (DB ? 2 : 1) * C::IPW * C::NPAD : 1];
     // cut table of each item: bytes (C - cut_min) or, with RW, floats (C - c0)
     constexpr int CUTB = (RW ? 4 : 1) * C::IPW * C::N;
@@ -746,8 +1097,16 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     uint32_t pk0[RW ? 1 : NW], pkL[RW ? 1 : NW];
     float cf0[RW ? A : 1], cfL[RW ? A : 1];
     if constexpr (RW) {
-        load_cuts_rw<KL, GI, 0, A>(cf0, cutf, tau);
-        load_cuts_rw<KL, GI, SL, A>(cfL, cutf, tau);
+        if constexpr (XL) {
+            xload_cuts_rw<LayX0, A>(cf0, cutf, tau);
+            xload_cuts_rw<LayX1s, A>(cfL, cutf, tau);
+        } else {
+            load_cuts_rw<KL, GI, 0, A>(cf0, cutf, tau);
+            load_cuts_rw<KL, GI, SL, A>(cfL, cutf, tau);
+        }
+    } else if constexpr (XL) {
+        xload_cuts<LayX0, A>(pk0, cut, tau);
+        xload_cuts<LayX1s, A>(pkL, cut, tau);
     } else {
         load_cuts<KL, GI, 0, A>(pk0, cut, tau);
         load_cuts<KL, GI, SL, A>(pkL, cut, tau);
@@ -824,17 +1183,20 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
     int l1 = 1;
     if constexpr (ODD) {
         const float2 tk = mix0[0];
-        fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tk.x);
+        if constexpr (XL) xfwd_layer<true>(f, xb, tau, tk.x);
+        else fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tk.x);
         phase_desc(1, kpowK(tk.y));
         l1 = 2;
     }
     for (; l1 + 1 <= p - 1; l1 += 2) {
         const float2 ta = mix0[l1 - 1];
-        fwd_layer<KL, GI, false, FLIP>(f, xb, tau, ta.x);
+        if constexpr (XL) xfwd_layer<false>(f, xb, tau, ta.x);
+        else fwd_layer<KL, GI, false, FLIP>(f, xb, tau, ta.x);
         if constexpr (RW) phase_stage_rw(f, cfL, GPI(l1), kpowK(ta.y));
         else phase_stage(f, pkL, ROW(l1), kpowK(ta.y));
         const float2 tb = mix0[l1];
-        fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tb.x);
+        if constexpr (XL) xfwd_layer<true>(f, xb, tau, tb.x);
+        else fwd_layer<KL, GI, true, FLIP>(f, xb, tau, tb.x);
         phase_desc(l1 + 1, kpowK(tb.y));
     }
 
@@ -906,7 +1268,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
         auto last_layer = [&](auto dir) {
             constexpr bool D = decltype(dir)::value;
             const float2 tk = mix0[0];
-            const double b = unlayer<KL, GI, D, FLIP, DB, true>(f, lam, xb, xb2, tau, tk.x, tk.y);
+            double b;
+            if constexpr (XL) b = xunlayer<D, DB, true>(f, lam, xb, xb2, tau, tk.x, tk.y);
+            else b = unlayer<KL, GI, D, FLIP, DB, true>(f, lam, xb, xb2, tau, tk.x, tk.y);
             put(1 + p, HS * 2.0 * b);
             const float mu = kpowK(tk.y);
             const float sc = exp2f(-0.5f * K);
@@ -937,7 +1301,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             float mu;
             {
                 const float2 tk = mix0[ly - 2];
-                const double b = unlayer<KL, GI, true, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
+                double b;
+                if constexpr (XL) b = xunlayer<true, DB, false>(f, lam, xb, xb2, tau, tk.x, tk.y);
+                else b = unlayer<KL, GI, true, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
                 put(1 + p + ly - 2, HS * 2.0 * b);
                 mu = kpowK(tk.y);
             }
@@ -954,7 +1320,9 @@ k_fused(const ConeDev* __restrict__ cones, int64_t item_base, int64_t n_items,
             }
             {
                 const float2 tk = mix0[ly - 2];
-                const double b = unlayer<KL, GI, false, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
+                double b;
+                if constexpr (XL) b = xunlayer<false, DB, false>(f, lam, xb, xb2, tau, tk.x, tk.y);
+                else b = unlayer<KL, GI, false, FLIP, DB>(f, lam, xb, xb2, tau, tk.x, tk.y);
                 put(1 + p + ly - 2, HS * 2.0 * b);
                 mu = kpowK(tk.y);
             }
@@ -1022,12 +1390,14 @@ hipError_t launch_v(dim3 grid, dim3 block, size_t dyn, const ConeDev* cones, int
 }
 
 // Variants of the K-qubit kernel that differ from the default layout (Fz): 1 needs more
-// stored qubits than the default register bits minus one, 2 fewer threads per item than 256.
+// stored qubits than the default register bits minus one, 2 fewer threads per item than 256,
+// 3 (the exchange layouts) is the 14-qubit adjoint kernel only.
 template <int K>
 constexpr bool fused_variant_ok(bool grad, int v) {
     constexpr int KL = K >= 3 ? K - 1 : K;
     if (v == 0) return true;
     if (v == 1) return grad ? KL >= QAOA_FUSED_AB_GRAD : KL >= 5;
+    if (v == 3) return grad && K == 14 && QAOA_FUSED_AB_GRAD == 4;
     return grad ? Fz<KL, 1>::TPI < 256 : Fz<KL, 0>::TPI < 256;
 }
 
@@ -1049,18 +1419,22 @@ hipError_t launch_kv(bool grad, const ConeDev* cones, int64_t item_base, int64_t
         const dim3 grid(static_cast<unsigned>(std::min(max_blocks, blocks - b0)));
         const int64_t base = item_base + b0 * ipw;
         hipError_t e;
-        if (grad)
+        if (grad) {
             e = odd ? launch_v<K, true, true, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
                     : launch_v<K, true, false, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
-        else
+        } else if constexpr (V != 3) {
             e = odd ? launch_v<K, false, true, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st)
                     : launch_v<K, false, false, V>(grid, block, dyn, cones, base, n_items, cut, rowcap, ea, st);
+        } else {
+            return hipErrorInvalidValue;   // the exchange layouts exist for the adjoint only
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// variant: 0, 1, 2 (see Fz); a variant that does not apply to K runs the default
+// variant: 0, 1, 2, 3 (see Fz and fused_variant_ok); a variant that does not apply to K runs
+// the default
 template <int K>
 hipError_t launch_k(bool grad, int variant, const ConeDev* cones, int64_t item_base, int64_t n_items,
                     const uint8_t* cut, int32_t rowcap, const EvalArgs& ea, hipStream_t st) {
@@ -1071,6 +1445,10 @@ hipError_t launch_k(bool grad, int variant, const ConeDev* cones, int64_t item_b
     if (variant == 2 && fused_variant_ok<K>(grad, 2)) {
         if constexpr (Fz<(K >= 3 ? K - 1 : K), 0>::TPI < 256)
             return launch_kv<K, 2>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
+    }
+    if (variant == 3 && fused_variant_ok<K>(grad, 3)) {
+        if constexpr (K == 14 && QAOA_FUSED_AB_GRAD == 4)
+            return launch_kv<K, 3>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
     }
     return launch_kv<K, 0>(grad, cones, item_base, n_items, cut, rowcap, ea, st);
 }

@@ -218,3 +218,14 @@ def test_batch_plan_errors_name_the_instance():
     with pytest.raises(Q.QaoaError) as ei:
         Q.Plan.batch([], 1)
     assert ei.value.status == Q.QAOA_EINVAL
+
+
+def test_tune_range():
+    # tune: 0 (off), 1 (timed choices), 2..5 (a fixed layout variant); anything else is refused
+    import paper_2101_10296_amd as Q
+    g = W.circulant(12, (1,))
+    for t in (0, 1, 2, 5):
+        Q.Plan(g.n, g.edges, p=2, tune=t).close()
+    for t in (-1, 6):
+        with pytest.raises(Exception, match="tune"):
+            Q.Plan(g.n, g.edges, p=2, tune=t)

@@ -1,7 +1,8 @@
 """The run-time tuner and the layout variants it chooses between (GPU).
 
 Every workgroup layout variant (one register bit fewer per LDS stage; workgroups of at
-least 256 threads) is compared with the oracle on every cone size; plans built with
+least 256 threads; the register/lane exchange layouts of the 14-qubit adjoint kernel) is
+compared with the oracle on every cone size; plans built with
 tune=True are compared with the default layout to the parity tolerances, and the tuner's
 record lists a choice with a time for every candidate of each class it met.
 """
@@ -24,7 +25,7 @@ def Q():
     return Q
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("p", [2, 3])
 def test_layout_variants_every_cone_size(Q, variant, p):
     # stars K_{1,m}: one cone of m + 1 = 2..14 qubits, forced layout variant (tune = 2 + v)
@@ -38,8 +39,20 @@ def test_layout_variants_many_items(Q):
     # random 3-regular n = 160 at p = 2: cones of 10-14 qubits, 720 items with ragged tails
     g = W.random_regular(160, 3, 12)
     ga, be = W.draw_angles(3, 2, 93)
-    for variant in (1, 2):
+    for variant in (1, 2, 3):
         check_energy(Q, g, 2, ga, be, reduce=False, grad=True, plan_kw=dict(tune=2 + variant))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_exchange_layouts_every_depth(Q, p):
+    # the 14-qubit star (one 14-qubit cone) in the exchange layouts at p = 1..5: both layer
+    # directions, the walk over several undone layers and the last one; unit weights and
+    # Gaussian couplings (per-amplitude phases)
+    g = W.star(13)
+    ga, be = W.draw_angles(3, p, 130 + p)
+    check_energy(Q, g, p, ga, be, reduce=True, grad=True, plan_kw=dict(tune=5))
+    w = np.random.default_rng(p).normal(size=g.m)
+    check_energy(Q, g, p, ga, be, reduce=False, weights=w, grad=True, plan_kw=dict(tune=5))
 
 
 def test_tuned_plans_match_defaults(Q):
