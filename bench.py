@@ -29,13 +29,13 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "8e3b3f6644b881988c3505540a9a989cc05fcc003f04de6fd4910cbb56b9ffbb",
+HBM_TRAFFIC = {"sources_sha256": "edda29f04ac8afff82e5a12c18b5fd83ce11d53648f41b3a84df2cff00039c7c",
                "counted_over_algorithmic": 1.003}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
 # item (cut tables and phase rows read, five FP64 results written).
-FUSED_TRAFFIC = {"sources_sha256": "061d0a49400c4171a2c35259fe1af608145deb1340b868072fd6f209cd2c364e",
+FUSED_TRAFFIC = {"sources_sha256": "d7b6046b13d9d8f9c7f8e03d483c0bc88a00064e9ca83046f65e4eab729379cb",
                  "bytes_per_item": 298.6}
 
 
