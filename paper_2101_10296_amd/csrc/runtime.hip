@@ -379,6 +379,10 @@ qaoa_status ensure_device(qaoa_plan_s* P, std::string& msg) {
         put(o_id, hp.inst_delta.data(), hp.inst_delta.size() * sizeof(double));
         put(o_ones, ones.data(), ones.size() * sizeof(double));
         if (hp.realw) put(o_ewd, ewd.data(), ewd.size() * sizeof(double));
+        if (P->d_arena) {   // an earlier first call failed after allocating: start over
+            hipFree(P->d_arena);
+            P->d_arena = nullptr;
+        }
         QCHECK(hipMalloc(&P->d_arena, arena));
         QCHECK(hipMemcpy(P->d_arena, stage.data(), copied, hipMemcpyHostToDevice));
     }
