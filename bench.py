@@ -115,14 +115,15 @@ def hbm_bytes_per_item(k: int, p: int, grad: bool, ckpt: bool = False) -> float:
     later pass reads and writes it, the final pass only reads it (with the gradient it also
     writes lambda).  Reverse: every pass but the last reads and writes psi and lambda (with
     stored checkpoints, ckpt, it reads both and writes lambda only); the last (undoing the
-    first forward pass) only reads them.  p = 1 keeps no state.
+    first forward pass) only reads lambda (psi there is regenerated from the cut values).
+    p = 1 keeps no state.
     """
     if p == 1:
         return 0.0
     F = (p - 1) * (hbm_groups(k - 1) - 1)   # passes after the first (at least two groups)
     n = float(1 << (k - 1))
     if grad:
-        return n * (8 + 16 * (F - 1) + 16 + 16 + (24 if ckpt else 32) * (F - 1))
+        return n * (8 + 16 * (F - 1) + 16 + 8 + (24 if ckpt else 32) * (F - 1))
     return n * (8 + 16 * (F - 1) + 8)
 
 

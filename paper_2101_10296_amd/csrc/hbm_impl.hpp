@@ -106,7 +106,10 @@ struct PassArgs {
 //   CF 1  one tile:                 16 per state, 512 threads, <= 128 VGPRs (two per CU):
 //                                   adjoint passes, and the forward boundary passes (two
 //                                   mixers and a phase), which run faster at this occupancy
-//   CF 2  forward, tile pair:       16 per tile, 512 threads, <= 128 VGPRs
+//   CF 2  tile pair, two states:    16 per tile, 512 threads, <= 128 VGPRs (two per CU):
+//                                   forward passes, and the undo of the first forward pass,
+//                                   which holds lambda only (30 dwords spill, still 4 % faster
+//                                   than one workgroup per CU)
 //   CF 3  adjoint, tile pair:       16 per state and tile, 512 threads, one workgroup per CU
 //         (four states in registers; fewer amplitudes per thread spill at 1024 threads)
 #ifndef QAOA_HBM_CF3_AB
@@ -128,6 +131,7 @@ struct Hz {
 
 __host__ __device__ constexpr int pass_cf(int kind, bool g0) {
     if (!g0 && kind == FWD_BND_MIX) return 1;
+    if (g0 && kind == RV_GEN_MIX) return 2;   // two states (lambda pair; psi_0 regenerated)
     return (kind >= GR_GEN_FINAL ? 1 : 0) + ((g0 && kind != FWD_GEN_FINAL && kind != GR_GEN_FINAL) ? 2 : 0);
 }
 
@@ -893,7 +897,56 @@ k_pass(PassArgs pa) {
             }
         }
         // ------------------------------------------------------------ reverse passes
-        if constexpr (KIND == RV_GEN_MIX || KIND == RV_MIX || KIND == RV_BND_MIX) {
+        if constexpr (KIND == RV_GEN_MIX) {
+            // The undo of the first forward pass (group lb of layer 1, lb = 1): psi there is
+            // D_1 |+> mixed by this group, so it is neither loaded nor undone.  lambda alone is
+            // undone; D_1 |+> is regenerated from the cut values, and every term of this pass
+            // (the group's beta_1 inner products, the dropped qubit's with pairs, and gamma_1)
+            // is taken at that point, the start of layer 1 (X_j commutes with every mixer of
+            // its layer).  Layer 1 is then undone completely, so lambda carries 1/mu_1
+            // (mu_1 = |kappa_1|^k) and psi_0 its true norm: weight mu_1.
+            float2 lm[NT][A];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) load(lm[t], pa.lam, off[t], t);
+            const float2 tkb = mix0[pa.lb - 1];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) hmix_group<CF, G0, true, RIO>(lm[t], xb, tau, -tkb.x, pm);   // ends in layout 0
+            if constexpr (PAIR) hflip(lm[0], lm[1], -tkb.x);
+            const float mu = kpowK(tkb.y);
+            const float sc = exp2f(-0.5f * k);
+            // D_1 |+> of tile t, register r (layout 0)
+            auto psi0 = [&](int t, int r) {
+                if constexpr (RW) {
+                    const float2 v = rphase(GPI(0), CV(t)(r));
+                    return make_float2(sc * v.x, sc * v.y);
+                } else {
+                    const float2 v = row_first[cutv<A>(pk[t], r)];
+                    return make_float2(sc * v.x, sc * v.y);
+                }
+            };
+            float a = 0.f, b = 0.f;
+            if constexpr (PAIR) {
+                float b0 = 0.f, b1 = 0.f;
+#pragma unroll
+                for (int r = 0; r < A; ++r) {
+                    if (r & 1) xacc(b1, lm[0][r], lm[1][r], psi0(0, r), psi0(1, r));
+                    else xacc(b0, lm[0][r], lm[1][r], psi0(0, r), psi0(1, r));
+                    if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                }
+                b = b0 + b1;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                for (int r = 0; r < A; ++r) f[t][r] = psi0(t, r);
+                if constexpr (RW) a += cgrad_stage_cv<false>(f[t], lm[t], CV(t), 0.0, cd.c0, 1.f);
+                else a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
+                b += hip_group<CF, G0, DB>(f[t], lm[t], xb, tau, pm, xb2);
+            }
+            part[0] += 2.0 * static_cast<double>(mu) * static_cast<double>(b);
+            part[1] += 2.0 * static_cast<double>(mu) * static_cast<double>(a);
+        }
+        if constexpr (KIND == RV_MIX || KIND == RV_BND_MIX) {
             float2 lm[NT][A];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -953,15 +1006,7 @@ k_pass(PassArgs pa) {
                 if constexpr (PAIR) b += hunflip2(f[0], f[1], lm[0], lm[1], tkb.x, tkb.y, w);
                 part[0] += 2.0 * static_cast<double>(b);
                 const float mu = (pa.lb == p) ? k2p : kpowK(tkb.y);
-                if constexpr (KIND == RV_GEN_MIX) {
-                    float a = 0.f;
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        if constexpr (RW) a += cgrad_stage_cv<false>(f[t], lm[t], CV(t), 0.0, cd.c0, 1.f);
-                        else a += cgrad_stage<false>(f[t], lm[t], pk[t], row_first, cd.cut_min, 1.f);
-                    }
-                    part[1] += 2.0 * static_cast<double>(mu) * mu * a;
-                } else {
+                {
                     float a = 0.f;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
