@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "f4f04e35b0c7d884514450982be55b3d34daaedb9b37ccb24da2c2889ac30b17",
+HBM_TRAFFIC = {"sources_sha256": "f8a95d24353c3f181406e4380331489d8d6f1f45a577ec60ee4da56dfa66fad5",
                "counted_over_algorithmic": 1.031}
 
 

@@ -129,6 +129,20 @@ struct Hz {
     static constexpr int ROT_IOJ = 9 - AB;           // I/O layout of groups >= 1: lanes on tile bits 9..12, 0, 1
 };
 
+// Passes that load the next unit's states (tile or tile pair) into registers before working
+// on the current one, so that a workgroup's loads overlap its arithmetic: bit KIND for the
+// groups >= 1, bit 16 + KIND for group 0.  Only the forward boundary pass of the groups >= 1
+// has the registers for it (one state: 80 VGPRs, 116 with the next tile, two workgroups per
+// CU kept); measured over 20-30-qubit cones it cut the device-memory time by 4 %.  The
+// reverse passes hold two states: with the next unit's they need one workgroup per CU
+// (256 VGPRs), and ran 5-12 % slower that way.
+#ifndef QAOA_HBM_PF_MASK
+#define QAOA_HBM_PF_MASK (1 << FWD_BND_MIX)
+#endif
+__host__ __device__ constexpr bool pass_pf(int kind, bool g0) {
+    return ((QAOA_HBM_PF_MASK >> (kind + (g0 ? 16 : 0))) & 1) != 0;
+}
+
 __host__ __device__ constexpr int pass_cf(int kind, bool g0) {
     if (!g0 && kind == FWD_BND_MIX) return 1;
     if (g0 && kind == RV_GEN_MIX) return 2;   // two states (lambda pair; psi_0 regenerated)
@@ -592,11 +606,21 @@ k_pass(PassArgs pa) {
         for (int r = 0; r < A; ++r)
             *reinterpret_cast<float2*>(reinterpret_cast<char*>(buf + off + io_off(t ? A - 1 - r : r)) + tb) = v[r];
     };
+    // prefetch: the next unit's psi (and, reverse passes, lambda) while this unit is worked on
+    constexpr bool PF = pass_pf(KIND, G0);
+    constexpr int NPF = (KIND == RV_MIX || KIND == RV_BND_MIX) ? 2 : 1;
+    float2 nx[PF ? NPF : 1][PF ? NT : 1][PF ? A : 1];
+    (void)nx;
     float2* xb = xbuf;
     float2* xb2 = DB ? xbuf + H::NPAD : nullptr;
     const float2* mix0 = pa.ea.mix + ipt * p;
     auto kpowK = [&](float k2) { return exp2f(0.5f * k * log2f(k2)); };
-    const float k2p = mix0[p - 1].y;
+    // the angle-table entries the pass uses, read once (reads inside the unit loop would be
+    // vector loads queued behind the prefetched states)
+    auto mix_at = [&](int l) { return mix0[l < 1 ? 0 : (l > p ? p - 1 : l - 1)]; };
+    const float2 mxa = mix_at(pa.la), mxb = mix_at(pa.lb), mx1 = mix0[0], mxp = mix0[p - 1];
+    const float2 mxf = mix_at(pa.fix_layer);
+    const float k2p = mxp.y;
     constexpr int RL = HS::rot(HS::S - 1);   // last processing layout
 
     // Per-thread partial sums over the workgroup's tiles, reduced once at the end into the
@@ -628,7 +652,26 @@ k_pass(PassArgs pa) {
             }
         return x;
     };
+    // Outer bits of the units' tiles.  A workgroup's units are consecutive, so after the first
+    // the outer bits follow by a masked increment (tile u + 1) or decrement (the complemented
+    // tile of a pair, tiles - 1 - u, counts down) over the outer-bit mask: two scalar
+    // operations instead of a loop over the stored bits.
+    const uint64_t omask = ((uint64_t{1} << kh) - 1u) & ~static_cast<uint64_t>(tmask);
+    uint64_t xnext[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) xnext[t] = outer_of(t ? tiles - 1 - unit0 : unit0);
+    auto next_off = [&](int t) { return (static_cast<size_t>(bslot) << kh) + xnext[t]; };
+    (void)next_off;
 
+    // the first unit's states, loaded while the workgroup sets up its first unit; every unit
+    // takes its states from the prefetch registers, so no working register waits on a load
+    if constexpr (PF) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            load(nx[0][t], pa.phi_in, next_off(t), t);
+            if constexpr (NPF == 2) load(nx[NPF - 1][t], pa.lam, next_off(t), t);
+        }
+    }
     for (int64_t unit = unit0; unit < unit0 + pa.tpw; ++unit) {
         // ---- outer bits of the unit's tiles and their linear cut coefficients: an edge
         // between tile bit b and an outer bit o adds w (1 - 2 x_o) to lcoef[b] and w x_o to
@@ -636,7 +679,9 @@ k_pass(PassArgs pa) {
         // exact in any order).  Qubit k-1 is an outer bit fixed at 0.
         uint64_t xo[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) xo[t] = outer_of(t ? tiles - 1 - unit : unit);
+        for (int t = 0; t < NT; ++t) xo[t] = xnext[t];
+        xnext[0] = ((xnext[0] | ~omask) + 1u) & omask;
+        if constexpr (NT > 1) xnext[1] = (xnext[1] - 1u) & omask;
         uint32_t pk[NT][NW];
         // real weights: the thread's base value, the register-bit coefficients and the
         // thread bits of each tile in layout 0
@@ -762,7 +807,7 @@ k_pass(PassArgs pa) {
                 else gen_stage(f[t], pk[t], row_first, exp2f(-0.5f * k) * (p == 1 ? k2p : 1.f));
             }
             if constexpr (KIND == FWD_GEN_MIX) {
-                const float t1 = mix0[0].x;
+                const float t1 = mx1.x;
 #pragma unroll
                 for (int t = 0; t < NT; ++t) hmix_group<CF, G0, false, 0>(f[t], xb, tau, t1, pm);
                 if constexpr (PAIR) hflip(f[0], f[1], t1);
@@ -775,9 +820,20 @@ k_pass(PassArgs pa) {
             }
         }
         if constexpr (KIND == FWD_MIX || KIND == FWD_BND_MIX || KIND == FWD_BND_FINAL || KIND == GR_BND_FINAL) {
+            if constexpr (PF) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) load(f[t], pa.phi_in, off[t], t);
-            const float2 tka = mix0[pa.la - 1];
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < A; ++r) f[t][r] = nx[0][t][r];
+                if (unit + 1 < unit0 + pa.tpw) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) load(nx[0][t], pa.phi_in, next_off(t), t);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) load(f[t], pa.phi_in, off[t], t);
+            }
+            const float2 tka = mxa;
 #pragma unroll
             for (int t = 0; t < NT; ++t) hmix_group<CF, G0, true, RIO>(f[t], xb, tau, tka.x, pm);   // ends in rotation 0
             if constexpr (PAIR) hflip(f[0], f[1], tka.x);
@@ -795,7 +851,7 @@ k_pass(PassArgs pa) {
                 else phase_stage(f[t], pk[t], row_lb, kpowK(tka.y) * (pa.lb == p ? k2p : 1.f));
             }
             if constexpr (KIND == FWD_BND_MIX) {
-                const float tb = mix0[pa.lb - 1].x;
+                const float tb = mxb.x;
 #pragma unroll
                 for (int t = 0; t < NT; ++t) hmix_group<CF, G0, false, 0>(f[t], xb, tau, tb, pm);
                 if constexpr (PAIR) hflip(f[0], f[1], tb);
@@ -809,7 +865,7 @@ k_pass(PassArgs pa) {
         }
         // ------------------------------------------------------------ final layer
         if constexpr (FINAL) {
-            const float tp = mix0[p - 1].x;
+            const float tp = mxp.x;
             double zzp = 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -870,7 +926,7 @@ k_pass(PassArgs pa) {
                     // the group's qubits are taken at this point of the layer (both states
                     // at the scale |kappa|^-m0a: weight |kappa|^2m0a), and only lambda is
                     // then undone
-                    const float2 tka = mix0[pa.la - 1];
+                    const float2 tka = mxa;
                     const float w0 = exp2f(pa.m0a * log2f(tka.y));
                     float b = 0.f;
 #pragma unroll
@@ -908,7 +964,7 @@ k_pass(PassArgs pa) {
             float2 lm[NT][A];
 #pragma unroll
             for (int t = 0; t < NT; ++t) load(lm[t], pa.lam, off[t], t);
-            const float2 tkb = mix0[pa.lb - 1];
+            const float2 tkb = mxb;
 #pragma unroll
             for (int t = 0; t < NT; ++t) hmix_group<CF, G0, true, RIO>(lm[t], xb, tau, -tkb.x, pm);   // ends in layout 0
             if constexpr (PAIR) hflip(lm[0], lm[1], -tkb.x);
@@ -948,10 +1004,28 @@ k_pass(PassArgs pa) {
         }
         if constexpr (KIND == RV_MIX || KIND == RV_BND_MIX) {
             float2 lm[NT][A];
+            if constexpr (PF) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                load(f[t], pa.phi_in, off[t], t);
-                load(lm[t], pa.lam, off[t], t);
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < A; ++r) {
+                        f[t][r] = nx[0][t][r];
+                        lm[t][r] = nx[1][t][r];
+                    }
+                if (unit + 1 < unit0 + pa.tpw) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const size_t o = next_off(t);
+                        load(nx[0][t], pa.phi_in, o, t);
+                        load(nx[1][t], pa.lam, o, t);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    load(f[t], pa.phi_in, off[t], t);
+                    load(lm[t], pa.lam, off[t], t);
+                }
             }
             if (pa.fix_layer > 0) {
                 // psi read as the forward sweep left it (the first reverse pass, or every reverse
@@ -960,14 +1034,14 @@ k_pass(PassArgs pa) {
                 // far (m of them), where lambda carries 1/|kappa_l| per qubit of that layer
                 // undone (k - m): psi is rescaled by |kappa_l|^(2m - k) (host: fix_pow).  For
                 // the first reverse pass of the uncompute program m = k - 14.
-                const float sc = exp2f(0.5f * pa.fix_pow * log2f(mix0[pa.fix_layer - 1].y));
+                const float sc = exp2f(0.5f * pa.fix_pow * log2f(mxf.y));
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
                     for (int r = 0; r < A; ++r) f[t][r] = make_float2(sc * f[t][r].x, sc * f[t][r].y);
             }
             if constexpr (KIND == RV_MIX) {
-                const float2 tka = mix0[pa.la - 1];
+                const float2 tka = mxa;
                 const float w0 = exp2f(pa.m0a * log2f(tka.y));
                 float w = w0, b = 0.f;
 #pragma unroll
@@ -995,7 +1069,7 @@ k_pass(PassArgs pa) {
             } else {
                 // undo mixer lb (the first group of layer lb in forward order: after it, layer
                 // lb is completely undone), then gamma_lb
-                const float2 tkb = mix0[pa.lb - 1];
+                const float2 tkb = mxb;
                 const float w0 = exp2f(pa.m0b * log2f(tkb.y));
                 float w = w0, b = 0.f;
 #pragma unroll
@@ -1014,7 +1088,7 @@ k_pass(PassArgs pa) {
                         else a += cgrad_stage<true>(f[t], lm[t], pk[t], row_lb, cd.cut_min, mu);
                     }
                     part[1] += 2.0 * static_cast<double>(mu) * mu * a;
-                    const float2 tka = mix0[pa.la - 1];
+                    const float2 tka = mxa;
                     const float wa0 = exp2f(pa.m0a * log2f(tka.y));
                     float wa = wa0, ba = 0.f;
 #pragma unroll
