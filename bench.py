@@ -28,7 +28,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM traffic of the device-memory pass kernels over their algorithmic bytes, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
-# sources it was measured on: reported as null once they change.
+# sources (and build flags) it was measured on: reported as null once they change.
 HBM_TRAFFIC = {"sources_sha256": "4c3e9a36d0c7826ac6404532c4104c6d3b51432156726982d42a989e1a0dffd4",
                "counted_over_algorithmic": 1.031}
 
@@ -50,11 +50,12 @@ def sources_sha256(files) -> str:
 
 def hbm_sources_sha256() -> str:
     return sources_sha256(("paper_2101_10296_amd/csrc/hbm_impl.hpp", "paper_2101_10296_amd/csrc/hbm.hip",
-                           "paper_2101_10296_amd/csrc/fused_impl.hpp"))
+                           "paper_2101_10296_amd/csrc/fused_impl.hpp", "paper_2101_10296_amd/build.py"))
 
 
 def fused_sources_sha256() -> str:
-    return sources_sha256(("paper_2101_10296_amd/csrc/fused_impl.hpp", "paper_2101_10296_amd/csrc/fused_k14.hip"))
+    return sources_sha256(("paper_2101_10296_amd/csrc/fused_impl.hpp", "paper_2101_10296_amd/csrc/fused_k14.hip",
+                           "paper_2101_10296_amd/build.py"))
 
 
 def flops_model_8d(k: int, p: int) -> float:

@@ -27,6 +27,12 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-munsafe-fp-atomics", "-I", INCLUDE, "-I", CSRC]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
+# Per-source device flags.  The 14-qubit adjoint kernel is bound by vector-instruction issue
+# at two waves per SIMD; LLVM's max-ilp machine scheduler removes its register spills (28
+# bytes per thread with the default scheduler) and cut its launch by 3.7 % on MI355X, with
+# bit-identical results.  The same scheduler raises register counts of the smaller cones'
+# kernels past occupancy steps, and gained nothing measurable on the device-memory passes.
+SOURCE_FLAGS = {"fused_k14.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def _run(cmd):
@@ -46,7 +52,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         if f.endswith(".cpp"):
             steps.append(["g++"] + HOST_FLAGS + ["-c", src, "-o", obj])
         else:
-            steps.append([HIPCC] + DEVICE_FLAGS + ["-c", src, "-o", obj])
+            steps.append([HIPCC] + DEVICE_FLAGS + SOURCE_FLAGS.get(f, []) + ["-c", src, "-o", obj])
     jobs = jobs or min(8, os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, steps):
