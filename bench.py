@@ -29,14 +29,14 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --hbm-only --hbm-points 1 --copy-gib 4`
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources (and build flags) it was measured on: reported as null once they change.
-HBM_TRAFFIC = {"sources_sha256": "4c3e9a36d0c7826ac6404532c4104c6d3b51432156726982d42a989e1a0dffd4",
+HBM_TRAFFIC = {"sources_sha256": "fe95b2630654ddb90d6e5b9a8a14cbcbf6f76c4f49b29aeb2756a23dd7c1b9b1",
                "counted_over_algorithmic": 1.031}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
 # item (cut tables and phase rows read, five FP64 results written).
-FUSED_TRAFFIC = {"sources_sha256": "d7b6046b13d9d8f9c7f8e03d483c0bc88a00064e9ca83046f65e4eab729379cb",
-                 "bytes_per_item": 298.6}
+FUSED_TRAFFIC = {"sources_sha256": "a95bec3c946b07d2ac2745d366d5cc15b30f434ca46562838f583d13fd3ba120",
+                 "bytes_per_item": 297.8}
 
 
 def sources_sha256(files) -> str:
