@@ -30,7 +30,10 @@ PEAK_HBM_GBS = 8000.0
 # (counters scaled by a 4 GiB device copy; summary in profiles/).  Valid only for the kernel
 # sources (and build flags) it was measured on: reported as null once they change.
 HBM_TRAFFIC = {"sources_sha256": "fe95b2630654ddb90d6e5b9a8a14cbcbf6f76c4f49b29aeb2756a23dd7c1b9b1",
-               "counted_over_algorithmic": 1.031}
+               "counted_over_algorithmic": 1.031,
+               # the program with every cone-size class reading stored forward states
+               # (checkpoint_mode 2, --checkpoint-mode 2 in the counter runs)
+               "counted_over_algorithmic_ckpt": 1.035}
 
 
 # Same for the 14-qubit workgroup-resident adjoint kernel: counted bytes per (cone, point)
@@ -251,8 +254,9 @@ def hbm_measure(Q, torch, W, points: int, ckpt: int = 0) -> dict:
     pl.close()
     gbs = byts / (ms * 1e-3) / 1e9
     traffic = None   # counted HBM bytes of the timed evaluation, if the counters are current
-    if hbm_sources_sha256() == HBM_TRAFFIC["sources_sha256"] and not stored:
-        traffic = round(byts * HBM_TRAFFIC["counted_over_algorithmic"])
+    all_stored = info["checkpointed_classes"] == len(by_k)
+    if hbm_sources_sha256() == HBM_TRAFFIC["sources_sha256"] and (all_stored or not stored):
+        traffic = round(byts * HBM_TRAFFIC["counted_over_algorithmic_ckpt" if stored else "counted_over_algorithmic"])
     return {"workload": f"random 3-regular n=200 (seed 502), p=3, {points} point(s), energy+gradient, "
                         "300 cones of 20-30 qubits in device memory",
             "adjoint": ("forward states read from stored checkpoints (checkpoint_mode %d, %d of %d cone-size "
